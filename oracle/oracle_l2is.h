@@ -1,0 +1,117 @@
+/*
+ * CPU oracle for the L2-norm regularized incremental-stencil WENO scheme
+ * (Zhu & Hu, "A L2-norm regularized incremental-stencil WENO scheme for
+ * compressible flows", arXiv 1908.02464) applied to the compressible Euler
+ * equations on uniform 1D/2D/3D grids.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, scalar FP64 reference
+ * written from the paper.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no source with the
+ * GPU library and must never be used as a fallback for it.
+ *
+ * Layout of every state array: structure of arrays [nvar][nz][ny][nx],
+ * x fastest, interior cells only.  nvar = 2 + dim, with
+ * dim = 1 (ny == nz == 1), 2 (nz == 1, ny > 1) or 3 (nz > 1, ny > 1).
+ * Variables: rho, rho*u_x, [rho*u_y, [rho*u_z]], E.
+ *
+ * Return codes: 0 ok, < 0 invalid argument, 1 non-physical state found.
+ */
+#ifndef ORACLE_L2IS_H
+#define ORACLE_L2IS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_REFLECTIVE = 2 };
+enum { ORC_SPLIT_LLF = 0, ORC_SPLIT_LF = 1, ORC_SPLIT_ROE = 2 };
+enum {
+  ORC_HYB_PER_FIELD = 0,  /* linear flux for field s iff sigma^s < eps      */
+  ORC_HYB_PER_FACE = 1,   /* linear for all fields iff max_s sigma^s < eps  */
+  ORC_HYB_WENO_ONLY = 2,  /* never linear (pure regularized WENO-IS)        */
+  ORC_HYB_LINEAR_ONLY = 3 /* always linear (optimal upwind scheme)          */
+};
+
+typedef struct {
+  double cfl;       /* CFL number (Sec. 4: 0.5)                                */
+  double c_reg;     /* c in lambda = c * sigma, Eq.(32): 1                     */
+  double eps_w;     /* epsilon in the weights, Eq.(8)/(28): 1e-20              */
+  double thr_C;     /* C in the threshold eps = C (dx/L)^alpha, Eq.(35): 1     */
+  int thr_alpha;    /* alpha in Eq.(35): 3                                     */
+  int split;        /* ORC_SPLIT_*                                             */
+  int hybrid;       /* ORC_HYB_*                                               */
+  int bc[6];        /* x-, x+, y-, y+, z-, z+ : ORC_BC_*                       */
+  double thr_L[3];  /* characteristic length L per direction in Eq.(35)       */
+} orc_params;
+
+/* Fill defaults for a grid: thr_L[d] = n_d * dx, transmissive boundaries. */
+int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx);
+
+/* Scalar WENO-L2IS reconstruction at x_{j+1/2} from a[0..4] = f_{j-2..j+2}
+ * with regularization parameter lam (Eq.(5),(6),(11),(27),(28)).
+ * dbg (may be NULL) receives 17 values:
+ *   q0..q3, beta0..beta3, tau5, E0..E3, omega0..omega3. */
+double orc_weno_l2is(const double a[5], double lam, double eps_w, double *dbg);
+
+/* Roe average between UL and UR and the eigensystem of the Roe Jacobian along
+ * direction dir (0,1,2).  L and R are nvar x nvar row-major, L = R^{-1};
+ * column s of R is the right eigenvector of field s, row s of L the left one.
+ * Field order: u_n - c, u_n (entropy), shear fields (tangential momentum in
+ * increasing index order), u_n + c.  lam: eigenvalues per field.
+ * roe (may be NULL): rho~, u~_x, u~_y, u~_z, H~, c~ (6 values). */
+int orc_roe_eigen(int nvar, int dir, double gamma, const double *UL,
+                  const double *UR, double *L, double *R, double *lam,
+                  double *roe);
+
+/* Physical flux along dir of one state, and its primitive variables.
+ * prim (may be NULL): rho, u_x, u_y, u_z, p, c, H (7 values). */
+int orc_phys_flux(int nvar, int dir, double gamma, const double *U, double *F,
+                  double *prim);
+
+/* Numerical flux at one face x_{j+1/2} from the six states U6[m*nvar + i],
+ * m = 0..5 meaning cells j-2..j+3 (already with boundary ghosts applied).
+ * eps_thr is the switch threshold for this direction; alpha_lf (length nvar)
+ * is only read for ORC_SPLIT_LF.  flags[s] = 1 if field s took the linear flux;
+ * sigma[s] = detector value of Eq.(30).  flags/sigma may be NULL. */
+int orc_face_flux(int nvar, int dir, double gamma, const orc_params *p,
+                  double eps_thr, const double *alpha_lf, const double *U6,
+                  double *Fhat, unsigned char *flags, double *sigma);
+
+/* dU/dt of Eq.(19), summed over the active directions. */
+int orc_rhs(const double *U, int nx, int ny, int nz, double dx, double gamma,
+            const orc_params *p, double *dUdt);
+
+/* dU/dt at ncells selected cells only; cell[k] = x + nx*(y + ny*z).
+ * out[v*ncells + k].  For ORC_SPLIT_LF the global speeds are taken over the
+ * whole grid. */
+int orc_rhs_at(const double *U, int nx, int ny, int nz, double dx,
+               double gamma, const orc_params *p, int ncells,
+               const long long *cell, double *out);
+
+/* Per-face flags and detector values along dir for the whole grid.
+ * Layout [nvar][..] with n_dir + 1 faces along dir (face f between cells f-1
+ * and f), the other two extents unchanged, x fastest. */
+int orc_face_debug(const double *U, int nx, int ny, int nz, double dx,
+                   double gamma, const orc_params *p, int dir,
+                   unsigned char *flags, double *sigma);
+
+/* CFL time step dt = cfl * dx / max_cells sum_d (|u_d| + c).
+ * Returns 1 (and still writes dt) if some cell is non-physical. */
+int orc_cfl_dt(const double *U, int nx, int ny, int nz, double dx,
+               double gamma, double cfl, double *dt);
+
+/* One third-order SSP Runge-Kutta step in place.  dt_in > 0: use it;
+ * otherwise the CFL dt of the current state.  dt_used may be NULL. */
+int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
+             const orc_params *p, double dt_in, double *dt_used);
+
+/* Advance to t_end (last step clipped) or max_steps, whichever first.
+ * Returns the status of the last check. */
+int orc_run(double *U, int nx, int ny, int nz, double dx, double gamma,
+            const orc_params *p, double t_end, int max_steps, double *t_out,
+            int *steps_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
