@@ -1,0 +1,164 @@
+/*
+ * weno_l2is.h -- C ABI of the MI355X (gfx950) library for the right-hand
+ * side and SSP-RK3 update of the L2-norm regularized incremental-stencil WENO
+ * scheme (Zhu & Hu, arXiv 1908.02464) for the compressible Euler equations on
+ * uniform structured 1D/2D/3D grids.
+ *
+ * What is computed (paper references):
+ *   semi-discretization  dU/dt = -(F_{j+1/2} - F_{j-1/2}) / dx      Eq.(19)
+ *   per face: Roe average, eigensystem, characteristic projection,
+ *     flux splitting, WENO reconstruction, back projection          Sec. 2.3
+ *   candidate fluxes, smoothness indicators, reference tau5        Eq.(6),(11)
+ *   L2-norm error terms and regularized weights                    Eq.(27),(28)
+ *   discontinuity detector, regularization parameter               Eq.(30)-(32)
+ *   hybrid switch to the optimal linear upwind flux                Eq.(33)-(35)
+ *   third-order TVD Runge-Kutta with CFL 0.5                       Sec. 4
+ * Multi-D grids are treated dimension by dimension (the paper states 1D).
+ *
+ * Data layout (every state array): FP64, structure of arrays
+ * [nvar][nz][ny][nx], x fastest, interior cells only (no ghost layers),
+ * nvar = 2 + dim, dim = 1 if ny == nz == 1, 2 if nz == 1 < ny, 3 if nz > 1
+ * (nz > 1 requires ny > 1).  Variables: rho, rho*u_x, [rho*u_y, [rho*u_z]], E.
+ *
+ * Pointers named U, dUdt, U0 are DEVICE pointers on the current HIP device;
+ * the caller owns them.  The library owns its scratch (stage buffers, the
+ * device time-step word, status), allocated in *_create / *_admit and freed
+ * in *_destroy / *_fetch.
+ *
+ * Errors: every int-returning call returns 0 on success, a negative
+ * WL2_E_* code on invalid input or a HIP failure (nothing is enqueued then),
+ * or WL2_S_NONPHYSICAL (> 0) from the calls that report device status.  No
+ * call aborts or throws; weno_l2is_strerror names a code.
+ */
+#ifndef WENO_L2IS_H
+#define WENO_L2IS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WL2_OK = 0,
+  WL2_E_NULL = -1,        /* a required pointer is NULL                     */
+  WL2_E_SHAPE = -2,       /* n < 1, nz > 1 with ny == 1, or too large       */
+  WL2_E_PARAM = -3,       /* dx, gamma, cfl, thresholds or enums invalid    */
+  WL2_E_BC = -4,          /* unpaired periodic side, reflective with n < 3  */
+  WL2_E_HIP = -5,         /* a HIP runtime call failed                       */
+  WL2_E_NOMEM = -6,       /* device allocation failed                        */
+  WL2_E_BUDGET = -7,      /* batch: HBM budget or slot table exhausted      */
+  WL2_E_SLOT = -8,        /* batch: slot not in use / not finished           */
+  WL2_S_NONPHYSICAL = 1   /* rho <= 0, p <= 0 or non-finite state detected   */
+};
+
+enum { WL2_BC_PERIODIC = 0, WL2_BC_TRANSMISSIVE = 1, WL2_BC_REFLECTIVE = 2 };
+
+/* Flux-splitting speed alpha^s of Eq.(21): LLF = max over the six stencil
+ * cells of |lambda^s(U_m)| (the hot path); LF = max over the whole grid per
+ * direction, recomputed every stage; ROE = |lambda^s| of the Roe matrix. */
+enum { WL2_SPLIT_LLF = 0, WL2_SPLIT_LF = 1, WL2_SPLIT_ROE = 2 };
+
+/* Hybrid switch of Eq.(33)/(35): PER_FIELD = linear flux for field s iff
+ * sigma^s < eps (default); PER_FACE = linear for all fields iff
+ * max_s sigma^s < eps; WENO_ONLY = regularized WENO everywhere;
+ * LINEAR_ONLY = optimal linear upwind scheme everywhere. */
+enum { WL2_HYB_PER_FIELD = 0, WL2_HYB_PER_FACE = 1, WL2_HYB_WENO_ONLY = 2,
+       WL2_HYB_LINEAR_ONLY = 3 };
+
+typedef struct weno_l2is_params {
+  double cfl;       /* CFL number, 0.5 (Sec. 4)                               */
+  double c_reg;     /* c in lambda = c * sigma^s, Eq.(32): 1                  */
+  double eps_weno;  /* epsilon of the weights, Eq.(28): 1e-20                 */
+  double thr_C;     /* C of the threshold eps = C (dx/L)^alpha, Eq.(35): 1    */
+  int thr_alpha;    /* alpha of Eq.(35): 3                                    */
+  int split;        /* WL2_SPLIT_*                                            */
+  int hybrid;       /* WL2_HYB_*                                              */
+  int bc[6];        /* x-, x+, y-, y+, z-, z+ : WL2_BC_*; periodic is paired  */
+  double thr_L[3];  /* L of Eq.(35) per direction; default n_d * dx           */
+} weno_l2is_params;
+
+typedef struct weno_l2is_ctx weno_l2is_ctx;
+
+/* Defaults above for an nx*ny*nz grid of spacing dx, transmissive sides. */
+int weno_l2is_params_default(weno_l2is_params *p, int nx, int ny, int nz,
+                             double dx);
+
+/* Create a solver context for one grid.  hip_stream: hipStream_t (NULL =
+ * the null stream); all of the context's work is enqueued there.  Allocates
+ * the two RK stage buffers, one accumulator and a small control block. */
+int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma,
+                     const weno_l2is_params *p, void *hip_stream,
+                     weno_l2is_ctx **out);
+
+/* Right-hand side of Eq.(19): dUdt = -sum_d (F_{j+1/2} - F_{j-1/2})_d / dx,
+ * for the state U (device).  Stateless form: enqueued on the null stream,
+ * asynchronous; an internal context per shape is cached and reused.
+ * U and dUdt must not overlap. */
+int weno_l2is_rhs(const double *U, int nx, int ny, int nz, double dx,
+                  double gamma, const weno_l2is_params *params, double *dUdt);
+
+/* The same on a context (its stream and scratch). */
+int weno_l2is_rhs_ctx(weno_l2is_ctx *ctx, const double *U, double *dUdt);
+
+/* One SSP-RK3 step of U in place (Shu-Osher form:
+ *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+ *   U  = 1/3 U + 2/3 (U2 + dt L(U2))).
+ * dt > 0: use it.  dt <= 0: the CFL step cfl*dx / max_cells sum_d(|u_d|+c)
+ * is reduced on the device from U (no host round trip) and non-physical
+ * cells set the status word.  Asynchronous on the context's stream. */
+int weno_l2is_step(weno_l2is_ctx *ctx, double *U, double dt);
+
+/* Advance U by n_steps CFL steps (dt from the device each step), stopping
+ * exactly at t_end (> 0; the last step is clipped, later steps are no-ops).
+ * The simulated time is kept on the device and read by weno_l2is_time. */
+int weno_l2is_advance(weno_l2is_ctx *ctx, double *U, int n_steps,
+                      double t_end);
+
+/* Reset the device clock of the context to t (for weno_l2is_advance). */
+int weno_l2is_set_time(weno_l2is_ctx *ctx, double t);
+
+/* CFL time step of U (device reduction).  If dt_host is not NULL the call
+ * synchronizes the stream and stores it.  Returns WL2_S_NONPHYSICAL if a
+ * non-physical cell was found (only known when dt_host != NULL). */
+int weno_l2is_cfl_dt(weno_l2is_ctx *ctx, const double *U, double *dt_host);
+
+/* Synchronize and read the dt used by the latest step and the device clock. */
+int weno_l2is_time(weno_l2is_ctx *ctx, double *t_host, double *last_dt_host);
+
+/* Per-face switch flags (1 = linear flux) and detector values sigma^s of
+ * Eq.(30) along direction dir, computed by the same device code as the
+ * sweeps.  Layout [nvar][..] with n_dir + 1 faces along dir (face f lies
+ * between cells f-1 and f), the other extents unchanged, x fastest; both
+ * are DEVICE pointers.  Asynchronous. */
+int weno_l2is_face_debug(weno_l2is_ctx *ctx, const double *U, int dir,
+                         unsigned char *flags, double *sigma);
+
+/* Synchronize and return the sticky status bits (bit 0: non-physical state
+ * seen by a CFL reduction).  Returns WL2_S_NONPHYSICAL if any bit is set.
+ * clear != 0 resets the bits. */
+int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
+
+/* Per-launch kernel timing with HIP events recorded on the context's stream
+ * around every kernel the context enqueues.  enable != 0 starts (and clears)
+ * collection; 0 stops it.  Costs two event records per launch. */
+int weno_l2is_timing_enable(weno_l2is_ctx *ctx, int enable);
+
+/* Synchronize and report the collected launches grouped by kernel: for
+ * k < *n_kernels (at most cap), names + 64*k holds a NUL-terminated kernel
+ * name, total_ms[k] the summed event time and launches[k] the count.  Any
+ * of names/total_ms/launches may be NULL to skip it. */
+int weno_l2is_timing_read(weno_l2is_ctx *ctx, int cap, char *names,
+                          double *total_ms, long long *launches,
+                          int *n_kernels);
+
+/* Free the context and its scratch (synchronizes its stream first). */
+void weno_l2is_destroy(weno_l2is_ctx *ctx);
+
+/* Static string for a return code. */
+const char *weno_l2is_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,179 @@
+// Small kernels around the sweeps: CFL reduction and time-step finalisation,
+// global Lax-Friedrichs speeds, and the per-face detector readback.
+#pragma once
+#include "wl2_device.hpp"
+
+namespace wl2 {
+
+constexpr int RED_BLOCK = 256;
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block maximum of non-negative values; NaN propagates (any NaN wins).
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const bool nan = (v != v);
+  v = wave_max(nan ? __longlong_as_double(0x7ff0000000000000LL) : v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// max over cells of sum_d (|u_d| + c), same operation order as the
+// definition dt = cfl dx / max_cells sum_d (|u_d| + c); contraction off so
+// the result is reproducible bit for bit.  Non-physical cells set status.
+template <int NV>
+__global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __restrict__ U,
+                                                               long long ncell, double gamma,
+                                                               StepCtl* ctl) {
+#pragma clang fp contract(off)
+  constexpr int DIM = NV - 2;
+  __shared__ double sh[RED_BLOCK / 64];
+  double smax = 0.0;
+  bool bad = false;
+  for (long long c = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * RED_BLOCK) {
+    const double rho = U[c], E = U[(NV - 1) * ncell + c];
+    double vel[DIM], q = 0.0;
+    bool fin = isfinite(rho) && isfinite(E);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double m = U[(1 + k) * ncell + c];
+      fin = fin && isfinite(m);
+      vel[k] = m / rho;
+      q += vel[k] * vel[k];
+    }
+    q *= 0.5;
+    const double p = (gamma - 1.0) * (E - rho * q);
+    const double cs = sqrt(gamma * p / rho);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s += fabs(vel[k]) + cs;
+    if (!fin || !(rho > 0.0) || !(p > 0.0)) bad = true;
+    if (s != s || s > smax) smax = s;
+  }
+  const double bm = block_max(smax, sh);
+  if (threadIdx.x == 0) {
+    if (bm > 0.0 || bm != bm)
+      atomicMax(&ctl->smax_bits, (unsigned long long)__double_as_longlong(bm));
+  }
+  if (bad) atomicOr(&ctl->status, 1u);
+}
+
+// dt = cfl dx / smax (or a fixed dt), clipped to the device clock when
+// use_clock; resets the running maximum for the next reduction.
+__global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / __longlong_as_double((long long)ctl->smax_bits);
+  if (use_clock) {
+    const double t = ctl->t, te = ctl->t_end;
+    if (!(t < te)) {
+      dt = 0.0;
+    } else {
+      if (t + dt > te) dt = te - t;
+      ctl->t = t + dt;
+    }
+  }
+  ctl->dt = dt;
+  ctl->smax_bits = 0ull;
+}
+
+// Program the device clock target (enqueued, no host synchronisation).
+__global__ void set_t_end_kernel(StepCtl* ctl, double t_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t_end = t_end;
+}
+
+// Global LF speeds along every active direction: max over cells of
+// |u_d - c|, |u_d|, |u_d + c| (fields u-c, entropy/shear, u+c).
+__global__ void lf_reset_kernel(StepCtl* ctl) {
+  if (threadIdx.x < 15) (&ctl->lf_bits[0][0])[threadIdx.x] = 0ull;
+}
+
+template <int NV>
+__global__ __launch_bounds__(RED_BLOCK) void lf_reduce_kernel(const double* __restrict__ U,
+                                                              long long ncell, double gamma,
+                                                              StepCtl* ctl) {
+  constexpr int DIM = NV - 2;
+  __shared__ double sh[RED_BLOCK / 64];
+  double mx[DIM][3];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) mx[d][0] = mx[d][1] = mx[d][2] = 0.0;
+  for (long long c = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * RED_BLOCK) {
+    const double rho = U[c], E = U[(NV - 1) * ncell + c];
+    const double ir = 1.0 / rho;
+    double vel[DIM], mu = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      vel[k] = U[(1 + k) * ncell + c] * ir;
+      mu += U[(1 + k) * ncell + c] * vel[k];
+    }
+    const double p = (gamma - 1.0) * (E - 0.5 * mu);
+    const double cs = sqrt(gamma * p * ir);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      mx[d][0] = fmax(mx[d][0], fabs(vel[d] - cs));
+      mx[d][1] = fmax(mx[d][1], fabs(vel[d]));
+      mx[d][2] = fmax(mx[d][2], fabs(vel[d] + cs));
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double bm = block_max(mx[d][j], sh);
+      if (threadIdx.x == 0) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(bm);
+        if (j == 0) atomicMax(&ctl->lf_bits[d][0], b);
+        if (j == 2) atomicMax(&ctl->lf_bits[d][NV - 1], b);
+        if (j == 1)
+          for (int k = 1; k < NV - 1; ++k) atomicMax(&ctl->lf_bits[d][k], b);
+      }
+    }
+  }
+}
+
+// One thread per face along DIR: switch flags and detector values.
+template <int NV, int DIR>
+__global__ __launch_bounds__(256) void face_debug_kernel(const double* __restrict__ U, KGrid g,
+                                                         KPhys ph, unsigned char* __restrict__ flags,
+                                                         double* __restrict__ sigma,
+                                                         long long nface) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= nface) return;
+  int fn[3] = {g.n[0], g.n[1], g.n[2]};
+  fn[DIR] += 1;
+  const int x = (int)(id % fn[0]);
+  const int y = (int)((id / fn[0]) % fn[1]);
+  const int z = (int)(id / ((long long)fn[0] * fn[1]));
+  int ci[3] = {x, y, z};
+  const int f = ci[DIR];
+  ci[DIR] = 0;
+  const long long base = ci[0] + (long long)ci[1] * g.stride[1] + (long long)ci[2] * g.stride[2];
+  CellRec<NV> c[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    double u[NV];
+    load_state<NV, DIR>(U, g, base, f - 3 + m, u);
+    make_rec<NV, DIR>(u, ph, c[m]);
+  }
+  double sig[NV];
+  const unsigned weno = face_detector<NV, DIR>(c[0], c[1], c[2], c[3], c[4], c[5], ph,
+                                               ph.eps_thr[DIR], sig);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    flags[k * nface + id] = ((weno >> k) & 1u) ? 0 : 1;
+    sigma[k * nface + id] = sig[k];
+  }
+}
+
+}  // namespace wl2

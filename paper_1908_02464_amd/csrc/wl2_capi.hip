@@ -1,0 +1,494 @@
+// Host side of the C ABI declared in include/weno_l2is.h: argument
+// validation, context and scratch management, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/weno_l2is.h"
+#include "wl2_aux.hpp"
+#include "wl2_kernels.hpp"
+
+using namespace wl2;
+
+struct weno_l2is_ctx {
+  int n[3];
+  int dim, nvar;
+  long long ncell;
+  double dx, gamma;
+  weno_l2is_params p;
+  hipStream_t stream;
+  int device;
+  double* U1;
+  double* U2;
+  double* acc;
+  StepCtl* ctl;
+  KGrid g;
+  KPhys ph;
+  // optional per-launch event timing
+  bool timing;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;  // (kernel id, pool index of start event)
+  std::vector<std::string> knames;
+};
+
+namespace {
+
+constexpr int SEG = 8;  // cells per thread along the sweep
+
+// Timing: bracket a launch with two events of the pool.
+struct TimedLaunch {
+  weno_l2is_ctx* c;
+  int slot;
+  TimedLaunch(const weno_l2is_ctx* cc, const char* name) : c(const_cast<weno_l2is_ctx*>(cc)), slot(-1) {
+    if (!c->timing) return;
+    int id = -1;
+    for (size_t i = 0; i < c->knames.size(); ++i)
+      if (c->knames[i] == name) id = (int)i;
+    if (id < 0) {
+      id = (int)c->knames.size();
+      c->knames.push_back(name);
+    }
+    const size_t need = 2 * (c->ev_used.size() + 1);
+    while (c->ev_pool.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->ev_pool.push_back(e);
+    }
+    slot = (int)(2 * c->ev_used.size());
+    c->ev_used.emplace_back(id, slot);
+    hipEventRecord(c->ev_pool[slot], c->stream);
+  }
+  ~TimedLaunch() {
+    if (slot >= 0) hipEventRecord(c->ev_pool[slot + 1], c->stream);
+  }
+};
+
+template <int NV, int DIR, int OUT>
+const char* sweep_name() {
+  static const char* tab[3][3] = {{"sweep_x_write", "sweep_x_accum", "sweep_x_rk"},
+                                  {"sweep_y_write", "sweep_y_accum", "sweep_y_rk"},
+                                  {"sweep_z_write", "sweep_z_accum", "sweep_z_rk"}};
+  return tab[DIR][OUT];
+}
+
+int validate(int nx, int ny, int nz, double dx, double gamma, const weno_l2is_params* p) {
+  if (!p) return WL2_E_NULL;
+  if (nx < 1 || ny < 1 || nz < 1) return WL2_E_SHAPE;
+  if (nz > 1 && ny < 2) return WL2_E_SHAPE;
+  if ((long long)nx * ny * nz > (1LL << 40)) return WL2_E_SHAPE;
+  if (!(dx > 0.0) || !std::isfinite(dx) || !(gamma > 1.0) || !std::isfinite(gamma))
+    return WL2_E_PARAM;
+  if (!(p->cfl > 0.0) || !(p->c_reg >= 0.0) || !(p->eps_weno >= 0.0) || !(p->thr_C >= 0.0) ||
+      p->thr_alpha < 0 || p->thr_alpha > 64)
+    return WL2_E_PARAM;
+  if (p->split < 0 || p->split > 2 || p->hybrid < 0 || p->hybrid > 3) return WL2_E_PARAM;
+  const int dim = nz > 1 ? 3 : (ny > 1 ? 2 : 1);
+  const int n[3] = {nx, ny, nz};
+  for (int d = 0; d < dim; ++d) {
+    const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return WL2_E_BC;
+    if ((lo == WL2_BC_PERIODIC) != (hi == WL2_BC_PERIODIC)) return WL2_E_BC;
+    if ((lo == WL2_BC_REFLECTIVE || hi == WL2_BC_REFLECTIVE) && n[d] < 3) return WL2_E_BC;
+    if (!(p->thr_L[d] > 0.0)) return WL2_E_PARAM;
+  }
+  return WL2_OK;
+}
+
+void fill_desc(weno_l2is_ctx* c) {
+  for (int d = 0; d < 3; ++d) {
+    c->g.n[d] = c->n[d];
+    c->g.bc_lo[d] = c->p.bc[2 * d];
+    c->g.bc_hi[d] = c->p.bc[2 * d + 1];
+  }
+  c->g.stride[0] = 1;
+  c->g.stride[1] = c->n[0];
+  c->g.stride[2] = (long long)c->n[0] * c->n[1];
+  c->g.ncell = c->ncell;
+  c->ph.gamma = c->gamma;
+  c->ph.gm1 = c->gamma - 1.0;
+  c->ph.dx = c->dx;
+  c->ph.inv_dx = 1.0 / c->dx;
+  c->ph.cfl = c->p.cfl;
+  c->ph.c_reg = c->p.c_reg;
+  c->ph.eps_w = c->p.eps_weno;
+  for (int d = 0; d < 3; ++d) {
+    double e = c->p.thr_C;
+    const double r = c->dx / c->p.thr_L[d];
+    for (int k = 0; k < c->p.thr_alpha; ++k) e *= r;  // C (dx/L)^alpha, Eq.(35)
+    c->ph.eps_thr[d] = (d < c->dim) ? e : 0.0;
+  }
+  c->ph.split = c->p.split;
+  c->ph.hybrid = c->p.hybrid;
+}
+
+int hip_err(hipError_t e) { return e == hipSuccess ? WL2_OK : WL2_E_HIP; }
+
+template <int NV, int DIR, int OUT>
+hipError_t launch_sweep_t(const weno_l2is_ctx* c, const SweepArgs& a) {
+  const int n = c->n[DIR];
+  const int nseg = (n + SEG - 1) / SEG;
+  const long long nthreads = (long long)nseg * (c->ncell / n);
+  const long long blocks = (nthreads + SWEEP_BLOCK - 1) / SWEEP_BLOCK;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  TimedLaunch tl(c, sweep_name<NV, DIR, OUT>());
+  hipLaunchKernelGGL((sweep_kernel<NV, DIR, SEG, OUT>), dim3((unsigned)blocks), dim3(SWEEP_BLOCK),
+                     0, c->stream, a, c->g, c->ph, nseg, nthreads);
+  return hipGetLastError();
+}
+
+template <int NV, int OUT>
+hipError_t launch_sweep_nv(const weno_l2is_ctx* c, int dir, const SweepArgs& a) {
+  if (dir == 0) return launch_sweep_t<NV, 0, OUT>(c, a);
+  if (NV >= 4 && dir == 1) return launch_sweep_t<NV, (NV >= 4 ? 1 : 0), OUT>(c, a);
+  if (NV >= 5 && dir == 2) return launch_sweep_t<NV, (NV >= 5 ? 2 : 0), OUT>(c, a);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep(const weno_l2is_ctx* c, int dir, int out, const SweepArgs& a) {
+  switch (c->nvar * 3 + out) {
+    case 9 + OUT_WRITE: return launch_sweep_nv<3, OUT_WRITE>(c, dir, a);
+    case 9 + OUT_ACCUM: return launch_sweep_nv<3, OUT_ACCUM>(c, dir, a);
+    case 9 + OUT_RK: return launch_sweep_nv<3, OUT_RK>(c, dir, a);
+    case 12 + OUT_WRITE: return launch_sweep_nv<4, OUT_WRITE>(c, dir, a);
+    case 12 + OUT_ACCUM: return launch_sweep_nv<4, OUT_ACCUM>(c, dir, a);
+    case 12 + OUT_RK: return launch_sweep_nv<4, OUT_RK>(c, dir, a);
+    case 15 + OUT_WRITE: return launch_sweep_nv<5, OUT_WRITE>(c, dir, a);
+    case 15 + OUT_ACCUM: return launch_sweep_nv<5, OUT_ACCUM>(c, dir, a);
+    case 15 + OUT_RK: return launch_sweep_nv<5, OUT_RK>(c, dir, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+unsigned red_blocks(long long ncell) {
+  long long b = (ncell + RED_BLOCK - 1) / RED_BLOCK;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_cfl(const weno_l2is_ctx* c, const double* U, double dt_fixed, int use_clock) {
+  if (dt_fixed <= 0.0) {
+    const unsigned b = red_blocks(c->ncell);
+    TimedLaunch tl(c, "cfl_reduce");
+    switch (c->nvar) {
+      case 3: hipLaunchKernelGGL(cfl_reduce_kernel<3>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+      case 4: hipLaunchKernelGGL(cfl_reduce_kernel<4>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+      default: hipLaunchKernelGGL(cfl_reduce_kernel<5>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    TimedLaunch tl(c, "finalize_dt");
+    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, c->p.cfl * c->dx,
+                       dt_fixed, use_clock);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
+  hipLaunchKernelGGL(lf_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl);
+  const unsigned b = red_blocks(c->ncell);
+  switch (c->nvar) {
+    case 3: hipLaunchKernelGGL(lf_reduce_kernel<3>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+    case 4: hipLaunchKernelGGL(lf_reduce_kernel<4>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+    default: hipLaunchKernelGGL(lf_reduce_kernel<5>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+  }
+  return hipGetLastError();
+}
+
+// dU/dt of the state Uk into out (WRITE then ACCUM over directions).
+hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
+  hipError_t e;
+  if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
+  for (int d = 0; d < c->dim; ++d) {
+    SweepArgs a{Uk, out, nullptr, nullptr, c->ctl, 0.0, 1.0};
+    if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One RK stage: out = a Un + b (Uk + dt L(Uk)).
+hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, double* out,
+                 double ra, double rb) {
+  hipError_t e;
+  if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
+  for (int d = 0; d < c->dim - 1; ++d) {
+    SweepArgs a{Uk, c->acc, nullptr, nullptr, c->ctl, 0.0, 1.0};
+    if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
+  }
+  SweepArgs a{Uk, out, c->dim > 1 ? c->acc : nullptr, Un, c->ctl, ra, rb};
+  return launch_sweep(c, c->dim - 1, OUT_RK, a);
+}
+
+hipError_t rk3(const weno_l2is_ctx* c, double* U) {
+  hipError_t e;
+  if ((e = stage(c, U, nullptr, c->U1, 0.0, 1.0)) != hipSuccess) return e;
+  if ((e = stage(c, c->U1, U, c->U2, 0.75, 0.25)) != hipSuccess) return e;
+  return stage(c, c->U2, U, U, 1.0 / 3.0, 2.0 / 3.0);
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int, int>, weno_l2is_ctx*> g_cache;
+
+}  // namespace
+
+extern "C" {
+
+int weno_l2is_params_default(weno_l2is_params* p, int nx, int ny, int nz, double dx) {
+  if (!p) return WL2_E_NULL;
+  if (nx < 1 || ny < 1 || nz < 1) return WL2_E_SHAPE;
+  if (!(dx > 0.0)) return WL2_E_PARAM;
+  std::memset(p, 0, sizeof(*p));
+  p->cfl = 0.5;
+  p->c_reg = 1.0;
+  p->eps_weno = 1e-20;
+  p->thr_C = 1.0;
+  p->thr_alpha = 3;
+  p->split = WL2_SPLIT_LLF;
+  p->hybrid = WL2_HYB_PER_FIELD;
+  for (int i = 0; i < 6; ++i) p->bc[i] = WL2_BC_TRANSMISSIVE;
+  p->thr_L[0] = nx * dx;
+  p->thr_L[1] = ny * dx;
+  p->thr_L[2] = nz * dx;
+  return WL2_OK;
+}
+
+int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno_l2is_params* p,
+                     void* hip_stream, weno_l2is_ctx** out) {
+  if (!out) return WL2_E_NULL;
+  *out = nullptr;
+  int rc = validate(nx, ny, nz, dx, gamma, p);
+  if (rc) return rc;
+  weno_l2is_ctx* c = new (std::nothrow) weno_l2is_ctx();
+  if (!c) return WL2_E_NOMEM;
+  c->n[0] = nx;
+  c->n[1] = ny;
+  c->n[2] = nz;
+  c->dim = nz > 1 ? 3 : (ny > 1 ? 2 : 1);
+  c->nvar = c->dim + 2;
+  c->ncell = (long long)nx * ny * nz;
+  c->dx = dx;
+  c->gamma = gamma;
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return WL2_E_HIP;
+  }
+  fill_desc(c);
+  const size_t bytes = sizeof(double) * (size_t)c->ncell * c->nvar;
+  bool ok = hipMalloc(&c->U1, bytes) == hipSuccess && hipMalloc(&c->U2, bytes) == hipSuccess &&
+            hipMalloc(&c->acc, bytes) == hipSuccess &&
+            hipMalloc(&c->ctl, sizeof(StepCtl)) == hipSuccess;
+  if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
+  if (!ok) {
+    hipFree(c->U1);
+    hipFree(c->U2);
+    hipFree(c->acc);
+    hipFree(c->ctl);
+    delete c;
+    (void)hipGetLastError();
+    return WL2_E_NOMEM;
+  }
+  *out = c;
+  return WL2_OK;
+}
+
+void weno_l2is_destroy(weno_l2is_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  hipFree(c->U1);
+  hipFree(c->U2);
+  hipFree(c->acc);
+  hipFree(c->ctl);
+  delete c;
+}
+
+int weno_l2is_rhs_ctx(weno_l2is_ctx* c, const double* U, double* dUdt) {
+  if (!c || !U || !dUdt) return WL2_E_NULL;
+  return hip_err(rhs_into(c, U, dUdt));
+}
+
+int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gamma,
+                  const weno_l2is_params* params, double* dUdt) {
+  if (!U || !dUdt) return WL2_E_NULL;
+  int rc = validate(nx, ny, nz, dx, gamma, params);
+  if (rc) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WL2_E_HIP;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto key = std::make_tuple(nx, ny, nz, dev);
+  weno_l2is_ctx* c = nullptr;
+  auto it = g_cache.find(key);
+  if (it == g_cache.end()) {
+    rc = weno_l2is_create(nx, ny, nz, dx, gamma, params, nullptr, &c);
+    if (rc) return rc;
+    g_cache[key] = c;
+  } else {
+    c = it->second;
+    c->dx = dx;
+    c->gamma = gamma;
+    c->p = *params;
+    fill_desc(c);
+  }
+  return hip_err(rhs_into(c, U, dUdt));
+}
+
+int weno_l2is_step(weno_l2is_ctx* c, double* U, double dt) {
+  if (!c || !U) return WL2_E_NULL;
+  if (dt > 0.0 && !std::isfinite(dt)) return WL2_E_PARAM;
+  hipError_t e = launch_cfl(c, U, dt > 0.0 ? dt : 0.0, 0);
+  if (e == hipSuccess) e = rk3(c, U);
+  return hip_err(e);
+}
+
+int weno_l2is_advance(weno_l2is_ctx* c, double* U, int n_steps, double t_end) {
+  if (!c || !U) return WL2_E_NULL;
+  if (n_steps < 0 || !(t_end > 0.0) || !std::isfinite(t_end)) return WL2_E_PARAM;
+  hipLaunchKernelGGL(set_t_end_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t_end);
+  hipError_t e = hipGetLastError();
+  for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+    e = launch_cfl(c, U, 0.0, 1);
+    if (e == hipSuccess) e = rk3(c, U);
+  }
+  return hip_err(e);
+}
+
+int weno_l2is_set_time(weno_l2is_ctx* c, double t) {
+  if (!c) return WL2_E_NULL;
+  if (!std::isfinite(t)) return WL2_E_PARAM;
+  StepCtl h;
+  hipError_t e = hipMemcpyAsync(&h, c->ctl, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return WL2_E_HIP;
+  h.t = t;
+  e = hipMemcpyAsync(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return hip_err(e);
+}
+
+int weno_l2is_cfl_dt(weno_l2is_ctx* c, const double* U, double* dt_host) {
+  if (!c || !U) return WL2_E_NULL;
+  hipError_t e = launch_cfl(c, U, 0.0, 0);
+  if (e != hipSuccess) return WL2_E_HIP;
+  if (!dt_host) return WL2_OK;
+  StepCtl h;
+  e = hipMemcpyAsync(&h, c->ctl, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return WL2_E_HIP;
+  *dt_host = h.dt;
+  return (h.status & 1u) ? WL2_S_NONPHYSICAL : WL2_OK;
+}
+
+int weno_l2is_time(weno_l2is_ctx* c, double* t_host, double* last_dt_host) {
+  if (!c) return WL2_E_NULL;
+  StepCtl h;
+  hipError_t e = hipMemcpyAsync(&h, c->ctl, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return WL2_E_HIP;
+  if (t_host) *t_host = h.t;
+  if (last_dt_host) *last_dt_host = h.dt;
+  return WL2_OK;
+}
+
+int weno_l2is_face_debug(weno_l2is_ctx* c, const double* U, int dir, unsigned char* flags,
+                         double* sigma) {
+  if (!c || !U || !flags || !sigma) return WL2_E_NULL;
+  if (dir < 0 || dir >= c->dim) return WL2_E_PARAM;
+  long long nface = c->ncell / c->n[dir] * (c->n[dir] + 1);
+  const long long blocks = (nface + 255) / 256;
+  if (blocks > 0x7fffffffLL) return WL2_E_SHAPE;
+  const dim3 gr((unsigned)blocks), bl(256);
+#define WL2_DBG(NV, D) \
+  hipLaunchKernelGGL((face_debug_kernel<NV, D>), gr, bl, 0, c->stream, U, c->g, c->ph, flags, sigma, nface)
+  switch (c->nvar * 3 + dir) {
+    case 9: WL2_DBG(3, 0); break;
+    case 12: WL2_DBG(4, 0); break;
+    case 13: WL2_DBG(4, 1); break;
+    case 15: WL2_DBG(5, 0); break;
+    case 16: WL2_DBG(5, 1); break;
+    case 17: WL2_DBG(5, 2); break;
+    default: return WL2_E_PARAM;
+  }
+#undef WL2_DBG
+  return hip_err(hipGetLastError());
+}
+
+int weno_l2is_status(weno_l2is_ctx* c, unsigned* status_bits, int clear) {
+  if (!c) return WL2_E_NULL;
+  StepCtl h;
+  hipError_t e = hipMemcpyAsync(&h, c->ctl, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return WL2_E_HIP;
+  if (status_bits) *status_bits = h.status;
+  if (clear && h.status) {
+    const unsigned zero = 0;
+    e = hipMemcpyAsync(&c->ctl->status, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return WL2_E_HIP;
+  }
+  return h.status ? WL2_S_NONPHYSICAL : WL2_OK;
+}
+
+int weno_l2is_timing_enable(weno_l2is_ctx* c, int enable) {
+  if (!c) return WL2_E_NULL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return WL2_E_HIP;
+  c->ev_used.clear();
+  c->knames.clear();
+  c->timing = enable != 0;
+  return WL2_OK;
+}
+
+int weno_l2is_timing_read(weno_l2is_ctx* c, int cap, char* names, double* total_ms,
+                          long long* launches, int* n_kernels) {
+  if (!c || !n_kernels) return WL2_E_NULL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return WL2_E_HIP;
+  const int nk = (int)c->knames.size();
+  std::vector<double> tot(nk, 0.0);
+  std::vector<long long> cnt(nk, 0);
+  for (auto& u : c->ev_used) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]) != hipSuccess)
+      return WL2_E_HIP;
+    tot[u.first] += ms;
+    cnt[u.first] += 1;
+  }
+  const int m = nk < cap ? nk : cap;
+  for (int k = 0; k < m; ++k) {
+    if (names) {
+      std::strncpy(names + 64 * k, c->knames[k].c_str(), 63);
+      names[64 * k + 63] = 0;
+    }
+    if (total_ms) total_ms[k] = tot[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  *n_kernels = m;
+  return WL2_OK;
+}
+
+const char* weno_l2is_strerror(int code) {
+  switch (code) {
+    case WL2_OK: return "ok";
+    case WL2_E_NULL: return "required pointer is NULL";
+    case WL2_E_SHAPE: return "invalid grid shape";
+    case WL2_E_PARAM: return "invalid parameter";
+    case WL2_E_BC: return "invalid boundary conditions";
+    case WL2_E_HIP: return "HIP runtime error";
+    case WL2_E_NOMEM: return "device allocation failed";
+    case WL2_E_BUDGET: return "HBM budget or slot table exhausted";
+    case WL2_E_SLOT: return "slot not in use or not finished";
+    case WL2_S_NONPHYSICAL: return "non-physical state detected";
+  }
+  return "unknown code";
+}
+
+}  // extern "C"

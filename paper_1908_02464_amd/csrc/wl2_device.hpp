@@ -1,0 +1,429 @@
+// Device-side arithmetic of the L2-norm regularized incremental-stencil WENO
+// scheme (Zhu & Hu, arXiv 1908.02464) for the Euler equations, gfx950, FP64.
+//
+// Formulation used on the device (algebraically identical to the paper's
+// steps, arranged for few FP64 instructions):
+//  * Per cell, once per sweep: 1/rho, p, c, 1/sqrt(rho) and the flux F_d
+//    along the sweep direction (Eq.(17)-(18)).
+//  * Roe average (Sec. 2.3 step (1)) from the sqrt(rho) weights:
+//    w u = m / sqrt(rho), w H = (E + p) / sqrt(rho); 1/rho~ = product of the
+//    two 1/sqrt(rho), so the detector needs no division.
+//  * Left eigenvectors (step (2)) are never stored: L x is evaluated as
+//      K = u~ . m(x),  X = b2 x_rho + b1 (x_E - K),  Y = (u~_n x_rho - x_n)/c~
+//      (u-c): (X + Y)/2   entropy: x_rho - X   shear t: (x_t - u~_t x_rho)/c~
+//      (u+c): (X - Y)/2
+//    with b1 = (gamma-1)/c~^2, b2 = b1 |u~|^2/2, and R f likewise from
+//    S = f_{u-c} + f_0 + f_{u+c}.  Acoustic/entropy right eigenvectors have
+//    unit density component, shear ones are scaled by c~.
+//  * Linear branch (Eq.(34)): because sum_s R^s L^s = I, the face flux is
+//      F = Fc6 + R delta,  delta^s = alpha^s dv^s                 (linear s)
+//                          delta^s = f^s_WENO - L^s Fc6            (WENO s)
+//    with Fc6 the six-point central flux and dv = L dU5 / 60 the detector
+//    difference of Eq.(31).  The WENO part is added as a correction after
+//    the linear sweep so the common (smooth) path stays short.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wl2 {
+
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+enum { SPLIT_LLF = 0, SPLIT_LF = 1, SPLIT_ROE = 2 };
+enum { HYB_PER_FIELD = 0, HYB_PER_FACE = 1, HYB_WENO_ONLY = 2, HYB_LINEAR_ONLY = 3 };
+
+// Grid description passed by value to every kernel.
+struct KGrid {
+  int n[3];            // nx, ny, nz
+  long long stride[3]; // element stride of one step along x, y, z
+  long long ncell;     // nx*ny*nz, the stride between variables
+  int bc_lo[3], bc_hi[3];
+};
+
+// Physical and scheme constants passed by value.
+struct KPhys {
+  double gamma, gm1, dx, inv_dx, cfl;
+  double c_reg, eps_w;
+  double eps_thr[3];   // switch threshold C (dx/L_d)^alpha per direction
+  int split, hybrid;
+};
+
+// Device control block of one grid (time step, clock, status).
+struct StepCtl {
+  unsigned long long smax_bits;  // running max of sum_d(|u_d|+c) as raw bits
+  unsigned int status;           // sticky: bit 0 = non-physical state seen
+  unsigned int pad;
+  double dt;                     // dt of the step in flight
+  double t;                      // simulated time after the step in flight
+  double t_end;                  // > 0: clip the clock to it
+  unsigned long long lf_bits[3][5];  // global LF speeds (raw bits) per direction, field
+};
+
+// ---------------------------------------------------------------- ghosts
+// Interior index for a line position k in [-3, n+2]; *flip = 1 when the
+// ghost is a mirror image whose normal momentum changes sign.
+__device__ __forceinline__ int ghost_index(int k, int n, int lo, int hi, bool& flip) {
+  flip = false;
+  if (k >= 0 && k < n) return k;
+  if (k < 0) {
+    if (lo == BC_PERIODIC) { int r = k % n; return r < 0 ? r + n : r; }
+    if (lo == BC_TRANSMISSIVE) return 0;
+    flip = true;
+    return -1 - k;
+  }
+  if (hi == BC_PERIODIC) return k % n;
+  if (hi == BC_TRANSMISSIVE) return n - 1;
+  flip = true;
+  return 2 * n - 1 - k;
+}
+
+// Load the conserved state at line position k along DIR of the line whose
+// cell 0 is at element offset `base`.
+template <int NV, int DIR>
+__device__ __forceinline__ void load_state(const double* __restrict__ U, const KGrid& g,
+                                           long long base, int k, double (&u)[NV]) {
+  bool flip;
+  const int idx = ghost_index(k, g.n[DIR], g.bc_lo[DIR], g.bc_hi[DIR], flip);
+  const long long off = base + (long long)idx * g.stride[DIR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
+  if (flip) u[1 + DIR] = -u[1 + DIR];
+}
+
+// ---------------------------------------------------------------- cells
+template <int NV>
+struct CellRec {
+  double U[NV];  // conserved state
+  double F[NV];  // physical flux along the sweep direction
+  double un;     // normal velocity
+  double c;      // sound speed
+  double iw;     // 1/sqrt(rho)
+  double p;      // pressure
+};
+
+template <int NV, int DIR>
+__device__ __forceinline__ void make_rec(const double (&u)[NV], const KPhys& ph, CellRec<NV>& r) {
+  constexpr int DIM = NV - 2;
+  const double rho = u[0], E = u[NV - 1];
+  const double ir = 1.0 / rho;
+  double vel[DIM];
+  double mu = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    vel[k] = u[1 + k] * ir;
+    mu += u[1 + k] * vel[k];
+  }
+  const double p = ph.gm1 * (E - 0.5 * mu);
+  r.c = sqrt(ph.gamma * p * ir);
+  r.iw = sqrt(ir);
+  r.p = p;
+  r.un = vel[DIR];
+  const double mn = u[1 + DIR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) r.U[v] = u[v];
+  r.F[0] = mn;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) r.F[1 + k] = mn * vel[k] + (k == DIR ? p : 0.0);
+  r.F[NV - 1] = (E + p) * vel[DIR];
+}
+
+// ---------------------------------------------------------------- Roe state
+template <int NV>
+struct Roe {
+  double u[NV - 2];
+  double H, c, ic, q, b1, b2, irho;
+};
+
+template <int NV, int DIR>
+__device__ __forceinline__ void roe_average(const CellRec<NV>& L, const CellRec<NV>& R,
+                                            const KPhys& ph, Roe<NV>& s) {
+  constexpr int DIM = NV - 2;
+  const double wl = L.U[0] * L.iw, wr = R.U[0] * R.iw;
+  const double is = 1.0 / (wl + wr);
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    s.u[k] = (L.U[1 + k] * L.iw + R.U[1 + k] * R.iw) * is;
+    q += s.u[k] * s.u[k];
+  }
+  s.q = 0.5 * q;
+  s.H = ((L.U[NV - 1] + L.p) * L.iw + (R.U[NV - 1] + R.p) * R.iw) * is;
+  s.c = sqrt(ph.gm1 * (s.H - s.q));
+  s.ic = 1.0 / s.c;
+  s.b1 = ph.gm1 * s.ic * s.ic;
+  s.b2 = s.b1 * s.q;
+  s.irho = L.iw * R.iw;  // 1 / sqrt(rho_L rho_R)
+}
+
+// out = L x   (field order: u-c, entropy, shear..., u+c)
+template <int NV, int DIR>
+__device__ __forceinline__ void project(const Roe<NV>& s, const double (&x)[NV], double (&o)[NV]) {
+  constexpr int DIM = NV - 2;
+  double K = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) K += s.u[k] * x[1 + k];
+  const double X = s.b2 * x[0] + s.b1 * (x[NV - 1] - K);
+  const double Y = (s.u[DIR] * x[0] - x[1 + DIR]) * s.ic;
+  o[0] = 0.5 * (X + Y);
+  o[1] = x[0] - X;
+  int f = 2;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    if (k == DIR) continue;
+    o[f++] = (x[1 + k] - s.u[k] * x[0]) * s.ic;
+  }
+  o[NV - 1] = 0.5 * (X - Y);
+}
+
+// out = R f
+template <int NV, int DIR>
+__device__ __forceinline__ void back_project(const Roe<NV>& s, const double (&f)[NV], double (&o)[NV]) {
+  constexpr int DIM = NV - 2;
+  const double a = f[0], b = f[1], g = f[NV - 1];
+  const double S = a + b + g, D = s.c * (g - a);
+  o[0] = S;
+  double eE = s.H * (a + g) + s.u[DIR] * D + s.q * b;
+  int fi = 2;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    if (k == DIR) {
+      o[1 + k] = s.u[k] * S + D;
+    } else {
+      const double e = f[fi++];
+      o[1 + k] = s.u[k] * S + s.c * e;
+      eE += s.c * s.u[k] * e;
+    }
+  }
+  o[NV - 1] = eE;
+}
+
+// ---------------------------------------------------------------- face
+// Splitting speed per field.
+template <int NV, int DIR>
+__device__ __forceinline__ void split_speeds(const CellRec<NV>& c0, const CellRec<NV>& c1,
+                                             const CellRec<NV>& c2, const CellRec<NV>& c3,
+                                             const CellRec<NV>& c4, const CellRec<NV>& c5,
+                                             const Roe<NV>& s, const KPhys& ph,
+                                             const double* lf, double (&a)[NV]) {
+  if (ph.split == SPLIT_LLF) {
+    // max over the six stencil cells of |u_n - c|, |u_n|, |u_n + c|
+    double am = fabs(c0.un - c0.c), a0 = fabs(c0.un), ap = fabs(c0.un + c0.c);
+#define WL2_MX(C)                                 \
+  am = fmax(am, fabs((C).un - (C).c));            \
+  a0 = fmax(a0, fabs((C).un));                    \
+  ap = fmax(ap, fabs((C).un + (C).c));
+    WL2_MX(c1) WL2_MX(c2) WL2_MX(c3) WL2_MX(c4) WL2_MX(c5)
+#undef WL2_MX
+    a[0] = am;
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a[k] = a0;
+    a[NV - 1] = ap;
+  } else if (ph.split == SPLIT_ROE) {
+    a[0] = fabs(s.u[DIR] - s.c);
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
+    a[NV - 1] = fabs(s.u[DIR] + s.c);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] = lf[k];
+  }
+}
+
+// Linear-branch flux of one face (all fields as if linear) plus the switch
+// decision.  Returns the bit mask of fields that need the WENO flux.
+template <int NV, int DIR>
+__device__ __forceinline__ unsigned face_linear(const CellRec<NV>& c0, const CellRec<NV>& c1,
+                                                const CellRec<NV>& c2, const CellRec<NV>& c3,
+                                                const CellRec<NV>& c4, const CellRec<NV>& c5,
+                                                const KPhys& ph, double eps_thr, const double* lf,
+                                                double (&Fh)[NV]) {
+  Roe<NV> s;
+  roe_average<NV, DIR>(c2, c3, ph, s);
+  double dU5[NV], Fc6[NV];
+  constexpr double k60 = 1.0 / 60.0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    dU5[i] = (c0.U[i] - c5.U[i]) + 5.0 * (c4.U[i] - c1.U[i]) + 10.0 * (c2.U[i] - c3.U[i]);
+    Fc6[i] = ((c0.F[i] + c5.F[i]) - 8.0 * (c1.F[i] + c4.F[i]) + 37.0 * (c2.F[i] + c3.F[i])) * k60;
+  }
+  double dv[NV];
+  project<NV, DIR>(s, dU5, dv);
+  double a[NV];
+  split_speeds<NV, DIR>(c0, c1, c2, c3, c4, c5, s, ph, lf, a);
+  unsigned weno = 0;
+  double smax = 0.0;
+  double d[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    dv[k] *= k60;
+    const double t = dv[k] * s.irho;
+    const double sig = t * t;  // Eq.(30)
+    smax = fmax(smax, sig);
+    if (!(sig < eps_thr)) weno |= 1u << k;
+    d[k] = a[k] * dv[k];
+  }
+  if (ph.hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
+  else if (ph.hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
+  else if (ph.hybrid == HYB_LINEAR_ONLY) weno = 0u;
+  double Rd[NV];
+  back_project<NV, DIR>(s, d, Rd);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) Fh[i] = Fc6[i] + Rd[i];
+  return weno;
+}
+
+// Detector values and decisions only (for the debug readback).
+template <int NV, int DIR>
+__device__ __forceinline__ unsigned face_detector(const CellRec<NV>& c0, const CellRec<NV>& c1,
+                                                  const CellRec<NV>& c2, const CellRec<NV>& c3,
+                                                  const CellRec<NV>& c4, const CellRec<NV>& c5,
+                                                  const KPhys& ph, double eps_thr, double (&sig)[NV]) {
+  Roe<NV> s;
+  roe_average<NV, DIR>(c2, c3, ph, s);
+  double dU5[NV], dv[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    dU5[i] = (c0.U[i] - c5.U[i]) + 5.0 * (c4.U[i] - c1.U[i]) + 10.0 * (c2.U[i] - c3.U[i]);
+  project<NV, DIR>(s, dU5, dv);
+  unsigned weno = 0;
+  double smax = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double t = dv[k] * (1.0 / 60.0) * s.irho;
+    sig[k] = t * t;
+    smax = fmax(smax, sig[k]);
+    if (!(sig[k] < eps_thr)) weno |= 1u << k;
+  }
+  if (ph.hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
+  else if (ph.hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
+  else if (ph.hybrid == HYB_LINEAR_ONLY) weno = 0u;
+  return weno;
+}
+
+// ---------------------------------------------------------------- WENO-L2IS
+// Scalar reconstruction at x_{j+1/2} from f_{j-2..j+2} (Eq.(5),(6),(11),
+// (27),(28)), optimal weights d = (0.4, 0.2, 0.3, 0.1).
+__device__ __forceinline__ double weno_l2is(double fm2, double fm1, double f0, double fp1,
+                                            double fp2, double lam, double eps_w) {
+  const double q0 = 0.5 * (f0 + fp1);
+  const double q1 = 0.5 * (3.0 * f0 - fm1);
+  const double q2 = (2.0 * f0 + 5.0 * fp1 - fp2) * (1.0 / 6.0);
+  const double q3 = (2.0 * fm2 - 7.0 * fm1 + 11.0 * f0) * (1.0 / 6.0);
+  const double d0 = fp1 - f0, d1 = f0 - fm1;
+  const double b0 = d0 * d0, b1 = d1 * d1;
+  const double s2a = f0 - 2.0 * fp1 + fp2, s2b = 3.0 * f0 - 4.0 * fp1 + fp2;
+  const double s3a = fm2 - 2.0 * fm1 + f0, s3b = fm2 - 4.0 * fm1 + 3.0 * f0;
+  const double b2 = (13.0 / 12.0) * s2a * s2a + 0.25 * s2b * s2b;
+  const double b3 = (13.0 / 12.0) * s3a * s3a + 0.25 * s3b * s3b;
+  const double t1 = (fp2 + fm2) - 4.0 * (fp1 + fm1) + 6.0 * f0;
+  const double t2 = (fp2 - fm2) - 2.0 * (fp1 - fm1);
+  const double tau5 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
+  const double e = fm1 - 2.0 * f0 + fp1;
+  const double E01 = e * e * (1.0 / 45.0);
+  const double lt = lam * tau5;
+  const double a0 = 0.4 * (1.0 + lt / (lam * b0 + E01 + eps_w));
+  const double a1 = 0.2 * (1.0 + lt / (lam * b1 + E01 + eps_w));
+  const double a2 = 0.3 * (1.0 + lt / (lam * b2 + eps_w));
+  const double a3 = 0.1 * (1.0 + lt / (lam * b3 + eps_w));
+  return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) / ((a0 + a1) + (a2 + a3));
+}
+
+// Row k of L (the left eigenvector of field k) as coefficients.
+template <int NV, int DIR, int K>
+__device__ __forceinline__ void left_row(const Roe<NV>& s, double (&r)[NV]) {
+  constexpr int DIM = NV - 2;
+  if (K == 0 || K == NV - 1) {
+    const double sg = (K == 0) ? 1.0 : -1.0;
+    r[0] = 0.5 * (s.b2 + sg * s.u[DIR] * s.ic);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) r[1 + k] = 0.5 * (-s.b1 * s.u[k] - (k == DIR ? sg * s.ic : 0.0));
+    r[NV - 1] = 0.5 * s.b1;
+  } else if (K == 1) {
+    r[0] = 1.0 - s.b2;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) r[1 + k] = s.b1 * s.u[k];
+    r[NV - 1] = -s.b1;
+  } else {
+    // shear field K-2: the (K-2)-th tangential momentum component
+    int t = K - 2;
+    int comp = (t < DIR) ? t : t + 1;
+    r[0] = -s.u[comp] * s.ic;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) r[1 + k] = (k == comp) ? s.ic : 0.0;
+    r[NV - 1] = 0.0;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ double dot(const double (&r)[NV], const double (&x)[NV]) {
+  double a = r[0] * x[0];
+#pragma unroll
+  for (int i = 1; i < NV; ++i) a += r[i] * x[i];
+  return a;
+}
+
+template <int NV, int DIR, int K>
+__device__ __forceinline__ double weno_field(const CellRec<NV>& c0, const CellRec<NV>& c1,
+                                             const CellRec<NV>& c2, const CellRec<NV>& c3,
+                                             const CellRec<NV>& c4, const CellRec<NV>& c5,
+                                             const Roe<NV>& s, double al, double dvk,
+                                             double LFk, const KPhys& ph) {
+  double r[NV];
+  left_row<NV, DIR, K>(s, r);
+  const double t = dvk * s.irho;
+  const double lam = ph.c_reg * (t * t);  // Eq.(32)
+  // f+-_m = (g_m +- alpha v_m)/2, v = L^K U_m, g = L^K F_m  (Eq.(20)-(21))
+#define WL2_SPL(C, P, M)                        \
+  {                                             \
+    const double vv = dot<NV>(r, (C).U);        \
+    const double gg = dot<NV>(r, (C).F);        \
+    P = 0.5 * (gg + al * vv);                   \
+    M = 0.5 * (gg - al * vv);                   \
+  }
+  double p0, p1, p2, p3, p4, p5, m0, m1, m2, m3, m4, m5;
+  WL2_SPL(c0, p0, m0) WL2_SPL(c1, p1, m1) WL2_SPL(c2, p2, m2)
+  WL2_SPL(c3, p3, m3) WL2_SPL(c4, p4, m4) WL2_SPL(c5, p5, m5)
+#undef WL2_SPL
+  (void)p5;
+  (void)m0;
+  // f+ on (f+_{j-2..j+2}); f- on the mirrored (f-_{j+3..j-1})  (Eq.(22)-(23))
+  const double fw = weno_l2is(p0, p1, p2, p3, p4, lam, ph.eps_w) +
+                    weno_l2is(m5, m4, m3, m2, m1, lam, ph.eps_w);
+  return fw - (LFk + al * dvk);
+}
+
+// Correction R (f_WENO - f_lin) of one face for the fields in `mask`.  Added
+// to the linear flux it gives the hybrid flux of Eq.(33) (per-field switch).
+template <int NV, int DIR>
+__device__ __forceinline__ void face_weno_correction(const CellRec<NV>& c0, const CellRec<NV>& c1,
+                                                     const CellRec<NV>& c2, const CellRec<NV>& c3,
+                                                     const CellRec<NV>& c4, const CellRec<NV>& c5,
+                                                     unsigned mask, const KPhys& ph,
+                                                     const double* lf, double (&dF)[NV]) {
+  Roe<NV> s;
+  roe_average<NV, DIR>(c2, c3, ph, s);
+  double dU5[NV], Fc6[NV];
+  constexpr double k60 = 1.0 / 60.0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    dU5[i] = (c0.U[i] - c5.U[i]) + 5.0 * (c4.U[i] - c1.U[i]) + 10.0 * (c2.U[i] - c3.U[i]);
+    Fc6[i] = ((c0.F[i] + c5.F[i]) - 8.0 * (c1.F[i] + c4.F[i]) + 37.0 * (c2.F[i] + c3.F[i])) * k60;
+  }
+  double dv[NV], LF[NV], a[NV];
+  project<NV, DIR>(s, dU5, dv);
+  project<NV, DIR>(s, Fc6, LF);
+  split_speeds<NV, DIR>(c0, c1, c2, c3, c4, c5, s, ph, lf, a);
+  double del[NV];
+#define WL2_FIELD(K)                                                                   \
+  if (K < NV) {                                                                        \
+    del[K < NV ? K : 0] = 0.0;                                                         \
+    if ((mask >> K) & 1u)                                                              \
+      del[K < NV ? K : 0] = weno_field<NV, DIR, (K < NV ? K : 0)>(                     \
+          c0, c1, c2, c3, c4, c5, s, a[K < NV ? K : 0], dv[K < NV ? K : 0] * k60,      \
+          LF[K < NV ? K : 0], ph);                                                     \
+  }
+  WL2_FIELD(0) WL2_FIELD(1) WL2_FIELD(2) WL2_FIELD(3) WL2_FIELD(4)
+#undef WL2_FIELD
+  back_project<NV, DIR>(s, del, dF);
+}
+
+}  // namespace wl2
