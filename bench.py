@@ -58,8 +58,14 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--hybrid", type=int, default=0, help="0 per-field (paper), 2 WENO only, 3 linear only")
+    ap.add_argument("--path", type=int, default=0,
+                    help="kernel path: 0 auto (fused stage kernel), 1 per-direction sweeps")
+    ap.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup (0 = auto)")
+    ap.add_argument("--wpe", type=int, default=0, help="fused kernel waves per SIMD (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of a state array (known bytes) for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -77,6 +83,7 @@ def main():
     params = capi.params_default(N, N, N, dx, bc=[0] * 6, hybrid=args.hybrid)
     stream = torch.cuda.current_stream()
     ctx = capi.Context(N, N, N, dx, GAMMA, params, stream)
+    ctx.tune(args.path, args.zchunk, args.wpe)
     Ud = torch.from_numpy(U0).cuda()
 
     log(f"[bench] warmup {args.warmup} steps")
@@ -110,10 +117,14 @@ def main():
     dom_ms, dom_n = kt[dom]
     avg_ms = dom_ms / dom_n
     arr = nvar * ncell * 8  # bytes of one state array
-    # algorithmic bytes the kernel's role must move per launch:
-    #   x sweep: read U, write partial sum; y sweep: read U, read+write partial;
-    #   z sweep + RK: read U^(k), partial sum, U^n (stages 2, 3), write U^(k+1)
-    role_arrays = {"sweep_x_write": 2.0, "sweep_y_accum": 3.0, "sweep_z_rk": 11.0 / 3.0,
+    # algorithmic bytes per launch.  Fused stage kernel: the method's own
+    # 8/3 state arrays per cell-stage (stage 1 reads U^n, writes U^(1);
+    # stages 2, 3 read U^(k) and U^n, write U^(k+1)), averaged over the three
+    # launches of a step.  Per-direction sweeps: the arrays each kernel's role
+    # must move (x: read U, write partial; y: read U, read+write partial;
+    # z + RK: read U^(k), partial, U^n in stages 2-3, write U^(k+1)).
+    role_arrays = {"fused3d_rk": 8.0 / 3.0,
+                   "sweep_x_write": 2.0, "sweep_y_accum": 3.0, "sweep_z_rk": 11.0 / 3.0,
                    "sweep_x_accum": 3.0, "sweep_y_write": 2.0, "sweep_z_accum": 3.0}
     dom_bytes = role_arrays.get(dom, 2.0) * arr
     achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
@@ -133,6 +144,11 @@ def main():
         weno_frac.append(float((lin_all == 0).double().mean().item()))
         del fl, sg
     torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        cp = Ud.clone()  # reads and writes exactly one state array
+        torch.cuda.synchronize()
+        del cp
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -158,6 +174,7 @@ def main():
                         "CFL 0.5, device CFL dt, WENO-L2IS hybrid (LLF)",
             "cells": ncell, "rk_stages_per_step": 3, "seed": SEED,
             "hybrid": {0: "per-field", 1: "per-face", 2: "weno-only", 3: "linear-only"}[args.hybrid],
+            "kernel_path": {0: "fused stage kernel", 1: "per-direction sweeps"}[args.path],
             "weno_face_fraction_xyz": [round(f, 6) for f in weno_frac],
         },
         "roofline": {

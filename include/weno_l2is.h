@@ -139,6 +139,16 @@ int weno_l2is_face_debug(weno_l2is_ctx *ctx, const double *U, int dir,
  * clear != 0 resets the bits. */
 int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
 
+/* Kernel path and tuning of a context.  path: WL2_PATH_AUTO (fused
+ * single-pass stage kernel for 3D grids, per-direction sweeps otherwise),
+ * WL2_PATH_SWEEPS (per-direction sweeps everywhere), WL2_PATH_FUSED (fused
+ * kernel; 3D only, else WL2_E_PARAM).  zchunk: z planes per workgroup of the
+ * fused kernel (0 = automatic).  waves_per_simd: register budget of the
+ * fused kernel, 1 or 2 (0 = default 1).  Results of all paths agree to
+ * round-off. */
+enum { WL2_PATH_AUTO = 0, WL2_PATH_SWEEPS = 1, WL2_PATH_FUSED = 2 };
+int weno_l2is_tune(weno_l2is_ctx *ctx, int path, int zchunk, int waves_per_simd);
+
 /* Per-launch kernel timing with HIP events recorded on the context's stream
  * around every kernel the context enqueues.  enable != 0 starts (and clears)
  * collection; 0 stops it.  Costs two event records per launch. */

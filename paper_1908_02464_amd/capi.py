@@ -21,6 +21,7 @@ S_NONPHYSICAL = 1
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
+PATH_AUTO, PATH_SWEEPS, PATH_FUSED = 0, 1, 2
 
 
 class WenoL2ISError(RuntimeError):
@@ -65,6 +66,7 @@ def lib():
         "weno_l2is_time": (ip, [vp, C.POINTER(dp), C.POINTER(dp)]),
         "weno_l2is_face_debug": (ip, [vp, vp, ip, vp, vp]),
         "weno_l2is_status": (ip, [vp, C.POINTER(C.c_uint), ip]),
+        "weno_l2is_tune": (ip, [vp, ip, ip, ip]),
         "weno_l2is_timing_enable": (ip, [vp, ip]),
         "weno_l2is_timing_read": (ip, [vp, ip, C.c_char_p, C.POINTER(dp), C.POINTER(C.c_longlong),
                                        C.POINTER(ip)]),
@@ -174,6 +176,9 @@ class Context:
         bits = C.c_uint(0)
         _chk(lib().weno_l2is_status(self.h, C.byref(bits), int(clear)), "status", True)
         return bits.value
+
+    def tune(self, path: int = 0, zchunk: int = 0, waves_per_simd: int = 0):
+        _chk(lib().weno_l2is_tune(self.h, int(path), int(zchunk), int(waves_per_simd)), "tune")
 
     def timing(self, enable: bool):
         _chk(lib().weno_l2is_timing_enable(self.h, int(enable)), "timing_enable")

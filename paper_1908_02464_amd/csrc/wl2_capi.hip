@@ -13,6 +13,7 @@
 
 #include "../../include/weno_l2is.h"
 #include "wl2_aux.hpp"
+#include "wl2_fused.hpp"
 #include "wl2_kernels.hpp"
 
 using namespace wl2;
@@ -31,6 +32,9 @@ struct weno_l2is_ctx {
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
+  int path;    // WL2_PATH_*
+  int zchunk;  // fused kernel: planes per workgroup (0 = automatic)
+  int wpe;     // fused kernel: target waves per SIMD (1 or 2)
   // optional per-launch event timing
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -204,10 +208,54 @@ hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
   return hipGetLastError();
 }
 
+bool use_fused(const weno_l2is_ctx* c) { return c->dim == 3 && c->path != WL2_PATH_SWEEPS; }
+
+int fused_zchunk(const weno_l2is_ctx* c) {
+  if (c->zchunk > 0) return c->zchunk < c->n[2] ? c->zchunk : c->n[2];
+  // enough workgroups to fill 256 CUs several times, long enough marches
+  const long long tiles = (long long)((c->n[0] + FT_X - 1) / FT_X) * ((c->n[1] + FT_Y - 1) / FT_Y);
+  int zc = c->n[2];
+  while (zc > 16 && tiles * ((c->n[2] + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+  return zc;
+}
+
+hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
+                        const double* Un, double ra, double rb) {
+  FusedArgs a;
+  a.Uk = Uk;
+  a.out = out;
+  a.Un = Un;
+  a.ctl = c->ctl;
+  a.rk_a = ra;
+  a.rk_b = rb;
+  a.zc = fused_zchunk(c);
+  a.tiles_x = (c->n[0] + FT_X - 1) / FT_X;
+  a.tiles_y = (c->n[1] + FT_Y - 1) / FT_Y;
+  a.nzc = (c->n[2] + a.zc - 1) / a.zc;
+  const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nzc;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 gr((unsigned)blocks), bl(FT_THREADS);
+  if (out_kind == OUT_RK) {
+    TimedLaunch tl(c, "fused3d_rk");
+    if (c->wpe == 2)
+      hipLaunchKernelGGL((fused3d_kernel<OUT_RK, 2>), gr, bl, 0, c->stream, a, c->g, c->ph);
+    else
+      hipLaunchKernelGGL((fused3d_kernel<OUT_RK, 1>), gr, bl, 0, c->stream, a, c->g, c->ph);
+  } else {
+    TimedLaunch tl(c, "fused3d_rhs");
+    if (c->wpe == 2)
+      hipLaunchKernelGGL((fused3d_kernel<OUT_WRITE, 2>), gr, bl, 0, c->stream, a, c->g, c->ph);
+    else
+      hipLaunchKernelGGL((fused3d_kernel<OUT_WRITE, 1>), gr, bl, 0, c->stream, a, c->g, c->ph);
+  }
+  return hipGetLastError();
+}
+
 // dU/dt of the state Uk into out (WRITE then ACCUM over directions).
 hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
   hipError_t e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
+  if (use_fused(c)) return launch_fused(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
   for (int d = 0; d < c->dim; ++d) {
     SweepArgs a{Uk, out, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -220,6 +268,7 @@ hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, dou
                  double ra, double rb) {
   hipError_t e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
+  if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb);
   for (int d = 0; d < c->dim - 1; ++d) {
     SweepArgs a{Uk, c->acc, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -279,6 +328,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   c->gamma = gamma;
   c->p = *p;
   c->stream = (hipStream_t)hip_stream;
+  c->wpe = 1;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return WL2_E_HIP;
@@ -437,6 +487,17 @@ int weno_l2is_status(weno_l2is_ctx* c, unsigned* status_bits, int clear) {
     if (e != hipSuccess) return WL2_E_HIP;
   }
   return h.status ? WL2_S_NONPHYSICAL : WL2_OK;
+}
+
+int weno_l2is_tune(weno_l2is_ctx* c, int path, int zchunk, int waves_per_simd) {
+  if (!c) return WL2_E_NULL;
+  if (path < WL2_PATH_AUTO || path > WL2_PATH_FUSED || zchunk < 0) return WL2_E_PARAM;
+  if (waves_per_simd < 0 || waves_per_simd > 2) return WL2_E_PARAM;
+  if (path == WL2_PATH_FUSED && !(c->dim == 3 && c->nvar == 5)) return WL2_E_PARAM;
+  c->path = path;
+  c->zchunk = zchunk;
+  c->wpe = waves_per_simd == 0 ? 1 : waves_per_simd;
+  return WL2_OK;
 }
 
 int weno_l2is_timing_enable(weno_l2is_ctx* c, int enable) {

@@ -30,6 +30,9 @@ namespace wl2 {
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum { SPLIT_LLF = 0, SPLIT_LF = 1, SPLIT_ROE = 2 };
 enum { HYB_PER_FIELD = 0, HYB_PER_FACE = 1, HYB_WENO_ONLY = 2, HYB_LINEAR_ONLY = 3 };
+// What a stage kernel does with the face-flux difference dU of Eq.(19):
+// write it, add it to the output, or fuse it into the SSP-RK3 combination.
+enum { OUT_WRITE = 0, OUT_ACCUM = 1, OUT_RK = 2 };
 
 // Grid description passed by value to every kernel.
 struct KGrid {

@@ -16,8 +16,6 @@
 
 namespace wl2 {
 
-enum { OUT_WRITE = 0, OUT_ACCUM = 1, OUT_RK = 2 };
-
 struct SweepArgs {
   const double* Uk;    // stage input: the stencil source
   double* out;         // WRITE/ACCUM: dU/dt (or partial sum); RK: U^(k+1)

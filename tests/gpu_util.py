@@ -37,3 +37,16 @@ def params_pair(orc, capi, shape, dx, **kw):
     po = orc.params(nx, ny, nz, dx, **{("eps_w" if k == "eps_weno" else k): v for k, v in kw.items()})
     pg = capi.params_default(nx, ny, nz, dx, **kw)
     return po, pg
+
+
+def rhs_err(a: np.ndarray, b: np.ndarray, U: np.ndarray, dt: float) -> float:
+    """dU/dt difference in units of the state after one CFL step:
+    max over variables of max|a_c - b_c| * dt / max|U_c|.  (dU/dt itself may
+    be ~0 for a component by cancellation between directions, e.g. density
+    on a solenoidal field, so it is not a usable scale.)"""
+    worst = 0.0
+    for c in range(b.shape[0]):
+        s = float(np.abs(U[c]).max())
+        s = s if s > 0 else 1.0
+        worst = max(worst, float(np.abs(a[c] - b[c]).max()) * dt / s)
+    return worst
