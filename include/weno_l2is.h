@@ -144,7 +144,7 @@ int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
  * WL2_PATH_SWEEPS (per-direction sweeps everywhere), WL2_PATH_FUSED (fused
  * kernel; 3D only, else WL2_E_PARAM).  zchunk: z planes per workgroup of the
  * fused kernel (0 = automatic).  waves_per_simd: register budget of the
- * fused kernel, 1 or 2 (0 = default 1).  Results of all paths agree to
+ * fused kernel, 1 or 2 (0 = default 2).  Results of all paths agree to
  * round-off. */
 enum { WL2_PATH_AUTO = 0, WL2_PATH_SWEEPS = 1, WL2_PATH_FUSED = 2 };
 int weno_l2is_tune(weno_l2is_ctx *ctx, int path, int zchunk, int waves_per_simd);

@@ -29,6 +29,7 @@ struct weno_l2is_ctx {
   double* U1;
   double* U2;
   double* acc;
+  unsigned long long* list;  // 3D: cells next to faces needing the WENO flux
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
@@ -229,24 +230,48 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
   a.rk_a = ra;
   a.rk_b = rb;
   a.zc = fused_zchunk(c);
+  a.list = c->list;
+  a.list_n = &c->ctl->list_n;
   a.tiles_x = (c->n[0] + FT_X - 1) / FT_X;
   a.tiles_y = (c->n[1] + FT_Y - 1) / FT_Y;
-  a.nzc = (c->n[2] + a.zc - 1) / a.zc;
-  const long long blocks = (long long)a.tiles_x * a.tiles_y * a.nzc;
+  const long long nzc = (c->n[2] + a.zc - 1) / a.zc;
+  const long long blocks = (long long)a.tiles_x * a.tiles_y * nzc;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 gr((unsigned)blocks), bl(FT_THREADS);
+  // compile-time fast path for the paper's 1D/3D defaults: LLF splitting,
+  // per-field switch
+  const bool fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
+#define WL2_FUSED(O, W, S, H) \
+  hipLaunchKernelGGL((fused3d_kernel<O, W, S, H>), gr, bl, 0, c->stream, a, c->g, c->ph)
+  hipLaunchKernelGGL(reset_list_kernel, dim3(1), dim3(64), 0, c->stream, a.list_n);
+  {
+  TimedLaunch tl(c, out_kind == OUT_RK ? "fused3d_rk" : "fused3d_rhs");
   if (out_kind == OUT_RK) {
-    TimedLaunch tl(c, "fused3d_rk");
-    if (c->wpe == 2)
-      hipLaunchKernelGGL((fused3d_kernel<OUT_RK, 2>), gr, bl, 0, c->stream, a, c->g, c->ph);
-    else
-      hipLaunchKernelGGL((fused3d_kernel<OUT_RK, 1>), gr, bl, 0, c->stream, a, c->g, c->ph);
+    if (c->wpe == 2) {
+      if (fast) WL2_FUSED(OUT_RK, 2, 0, 0); else WL2_FUSED(OUT_RK, 2, -1, -1);
+    } else {
+      if (fast) WL2_FUSED(OUT_RK, 1, 0, 0); else WL2_FUSED(OUT_RK, 1, -1, -1);
+    }
   } else {
-    TimedLaunch tl(c, "fused3d_rhs");
-    if (c->wpe == 2)
-      hipLaunchKernelGGL((fused3d_kernel<OUT_WRITE, 2>), gr, bl, 0, c->stream, a, c->g, c->ph);
-    else
-      hipLaunchKernelGGL((fused3d_kernel<OUT_WRITE, 1>), gr, bl, 0, c->stream, a, c->g, c->ph);
+    if (c->wpe == 2) {
+      if (fast) WL2_FUSED(OUT_WRITE, 2, 0, 0); else WL2_FUSED(OUT_WRITE, 2, -1, -1);
+    } else {
+      if (fast) WL2_FUSED(OUT_WRITE, 1, 0, 0); else WL2_FUSED(OUT_WRITE, 1, -1, -1);
+    }
+  }
+  }
+#undef WL2_FUSED
+  // nonlinear corrections of the listed cells (an empty list exits at once)
+  {
+    TimedLaunch tl(c, "weno_fix3d");
+    const dim3 fg(1024), fb(128);
+#define WL2_FIX(O, S, H) hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H>), fg, fb, 0, c->stream, a, c->g, c->ph)
+    if (out_kind == OUT_RK) {
+      if (fast) WL2_FIX(OUT_RK, 0, 0); else WL2_FIX(OUT_RK, -1, -1);
+    } else {
+      if (fast) WL2_FIX(OUT_WRITE, 0, 0); else WL2_FIX(OUT_WRITE, -1, -1);
+    }
+#undef WL2_FIX
   }
   return hipGetLastError();
 }
@@ -328,7 +353,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   c->gamma = gamma;
   c->p = *p;
   c->stream = (hipStream_t)hip_stream;
-  c->wpe = 1;
+  c->wpe = 2;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return WL2_E_HIP;
@@ -338,11 +363,14 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   bool ok = hipMalloc(&c->U1, bytes) == hipSuccess && hipMalloc(&c->U2, bytes) == hipSuccess &&
             hipMalloc(&c->acc, bytes) == hipSuccess &&
             hipMalloc(&c->ctl, sizeof(StepCtl)) == hipSuccess;
+  if (ok && c->dim == 3)
+    ok = hipMalloc(&c->list, sizeof(unsigned long long) * (size_t)c->ncell) == hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
     hipFree(c->U1);
     hipFree(c->U2);
     hipFree(c->acc);
+    hipFree(c->list);
     hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
@@ -359,6 +387,7 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   hipFree(c->U1);
   hipFree(c->U2);
   hipFree(c->acc);
+  hipFree(c->list);
   hipFree(c->ctl);
   delete c;
 }
@@ -496,7 +525,7 @@ int weno_l2is_tune(weno_l2is_ctx* c, int path, int zchunk, int waves_per_simd) {
   if (path == WL2_PATH_FUSED && !(c->dim == 3 && c->nvar == 5)) return WL2_E_PARAM;
   c->path = path;
   c->zchunk = zchunk;
-  c->wpe = waves_per_simd == 0 ? 1 : waves_per_simd;
+  c->wpe = waves_per_simd == 0 ? 2 : waves_per_simd;
   return WL2_OK;
 }
 

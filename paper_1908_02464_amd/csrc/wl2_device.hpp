@@ -59,6 +59,8 @@ struct StepCtl {
   double t;                      // simulated time after the step in flight
   double t_end;                  // > 0: clip the clock to it
   unsigned long long lf_bits[3][5];  // global LF speeds (raw bits) per direction, field
+  unsigned int list_n;           // entries in the nonlinear-correction list
+  unsigned int pad2;
 };
 
 // ---------------------------------------------------------------- ghosts

@@ -122,9 +122,13 @@ __device__ __forceinline__ void roe_light(const LRec<NV>& L, const LRec<NV>& R, 
 // of fields whose detector asks for the nonlinear flux.
 // `src.get(m, rec)` supplies stencil cell m = 0..5 (j-2 .. j+3); cells are
 // requested in the pairs (0,5), (1,4), (2,3) so only two are live at a time.
-template <int NV, int DIR, class Src>
+// SPLIT / HYB: compile-time splitting and switch modes, or -1 to read them
+// from ph at run time.
+template <int NV, int DIR, int SPLIT, int HYB, class Src>
 __device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& ph, double eps_thr,
                                                   const unsigned long long* lfb, double (&Fh)[NV]) {
+  const int split = SPLIT >= 0 ? SPLIT : ph.split;
+  const int hybrid = HYB >= 0 ? HYB : ph.hybrid;
   double dU5[NV], Fc6[NV];
   double am, a0, ap;
   LRec<NV> c2, c3;
@@ -178,12 +182,12 @@ __device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& p
   Roe<NV> s;
   roe_light<NV, DIR>(c2, c3, ph, s);
   double a[NV];
-  if (ph.split == SPLIT_LLF) {
+  if (split == SPLIT_LLF) {
     a[0] = am;
 #pragma unroll
     for (int k = 1; k < NV - 1; ++k) a[k] = a0;
     a[NV - 1] = ap;
-  } else if (ph.split == SPLIT_ROE) {
+  } else if (split == SPLIT_ROE) {
     a[0] = fabs(s.u[DIR] - s.c);
 #pragma unroll
     for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
@@ -205,9 +209,9 @@ __device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& p
     if (!(sig < eps_thr)) weno |= 1u << k;
     d[k] = a[k] * dv[k];
   }
-  if (ph.hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
-  else if (ph.hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
-  else if (ph.hybrid == HYB_LINEAR_ONLY) weno = 0u;
+  if (hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
+  else if (hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
+  else if (hybrid == HYB_LINEAR_ONLY) weno = 0u;
   double Rd[NV];
   back_project<NV, DIR>(s, d, Rd);
 #pragma unroll
@@ -226,7 +230,9 @@ struct FusedArgs {
   const StepCtl* ctl;
   double rk_a, rk_b;
   int zc;             // planes per workgroup
-  int tiles_x, tiles_y, nzc;
+  int tiles_x, tiles_y;
+  unsigned long long* list;  // cells next to a face that needs the WENO flux
+  unsigned int* list_n;      // number of entries in list
 };
 
 // Index of a line position clamped to [-3, n+2] and mapped through the
@@ -234,21 +240,6 @@ struct FusedArgs {
 __device__ __forceinline__ int ghost_clamped(int k, int n, int lo, int hi, bool& flip) {
   k = k < -3 ? -3 : (k > n + 2 ? n + 2 : k);
   return ghost_index(k, n, lo, hi, flip);
-}
-
-template <int NV>
-__device__ __forceinline__ void load_xyz(const double* __restrict__ U, const KGrid& g, int x, int y,
-                                         int z, double (&u)[NV]) {
-  bool fx, fy, fz;
-  const int ix = ghost_clamped(x, g.n[0], g.bc_lo[0], g.bc_hi[0], fx);
-  const int iy = ghost_clamped(y, g.n[1], g.bc_lo[1], g.bc_hi[1], fy);
-  const int iz = ghost_clamped(z, g.n[2], g.bc_lo[2], g.bc_hi[2], fz);
-  const long long off = ix + (long long)iy * g.stride[1] + (long long)iz * g.stride[2];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
-  if (fx) u[1] = -u[1];
-  if (fy) u[2] = -u[2];
-  if (fz) u[3] = -u[3];
 }
 
 template <int NV>
@@ -376,14 +367,64 @@ __device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, c
   back_project<NV, DIR>(s, del, dF);
 }
 
-// WPE: target waves per SIMD (1: no register spills; 2: twice the
-// resident waves with some spilling).  Picked per context by tuning.
-template <int OUT, int WPE>
+// Column of cells at fixed (x, y): element offset of its (x, y) position
+// after the boundary mapping, and the momentum signs of mirror ghosts.
+struct Col {
+  long long xy;
+  bool fx, fy;
+};
+
+__device__ __forceinline__ Col make_col(const KGrid& g, int x, int y) {
+  Col c;
+  const int ix = ghost_clamped(x, g.n[0], g.bc_lo[0], g.bc_hi[0], c.fx);
+  const int iy = ghost_clamped(y, g.n[1], g.bc_lo[1], g.bc_hi[1], c.fy);
+  c.xy = ix + (long long)iy * g.stride[1];
+  return c;
+}
+
+template <int NV>
+__device__ __forceinline__ void load_col(const double* __restrict__ U, const KGrid& g, const Col& c,
+                                         int z, double (&u)[NV]) {
+  bool fz = false;
+  const int iz = (z >= 0 && z < g.n[2]) ? z : ghost_clamped(z, g.n[2], g.bc_lo[2], g.bc_hi[2], fz);
+  const long long off = c.xy + (long long)iz * g.stride[2];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
+  if (c.fx) u[1] = -u[1];
+  if (c.fy) u[2] = -u[2];
+  if (fz) u[3] = -u[3];
+}
+
+// z stencil of a column owner: cells j-2, j-1 from the per-column LDS ring,
+// j .. j+3 from registers.
+template <int NV>
+struct ZSrc {
+  double (*swin)[NV + 3][FT_OWN];
+  int slot0, slot1, col;
+  const LRec<NV>&r0, &r1, &r2, &r3;
+  __device__ __forceinline__ void ring(int slot, LRec<NV>& r) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.U[v] = swin[slot][v][col];
+    r.p = swin[slot][NV][col];
+    r.c = swin[slot][NV + 1][col];
+    r.iw = swin[slot][NV + 2][col];
+  }
+  __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
+    if (m == 0) ring(slot0, r);
+    else if (m == 1) ring(slot1, r);
+    else r = m == 2 ? r0 : m == 3 ? r1 : m == 4 ? r2 : r3;
+  }
+};
+
+// WPE: target waves per SIMD.  SPLIT / HYB: compile-time modes (-1: runtime).
+template <int OUT, int WPE, int SPLIT, int HYB>
 __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
-  __shared__ double srec[NV + 3][FP_N];
-  __shared__ double sfx[NV][NXF];
-  __shared__ double sfy[NV][NYF];
+  __shared__ double srec[NV + 3][FP_N];      // plane z with halo
+  __shared__ double sfx[NV][NXF];            // x-face fluxes of plane z
+  __shared__ double sfy[NV][NYF];            // y-face fluxes of plane z
+  __shared__ double swin[2][NV + 3][FT_OWN]; // two oldest cells of each z window
+  __shared__ unsigned char sgx[NXF], sgy[NYF];  // face needs the nonlinear flux
 
   double dt = 0.0;
   if (OUT == OUT_RK) {
@@ -413,6 +454,8 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   const int gx = x0 + ox, gy = y0 + oy;
   const bool valid = owner && gx < g.n[0] && gy < g.n[1];
   const int lds_own = (oy + 3) * FP_X + (ox + 3);
+  const Col ocol = make_col(g, gx, gy);
+  const long long oout = (long long)gx + (long long)gy * g.stride[1];
 
   // halo cell of this thread (t < NHALO): tile-relative (hc, hr)
   int hc = 0, hr = 0;
@@ -427,55 +470,71 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     hr = k < 3 ? k - 3 : FT_Y + k - 3;
   }
   const int lds_halo = (hr + 3) * FP_X + (hc + 3);
+  const Col hcol = make_col(g, x0 + hc, y0 + hr);
 
-  // z window of the owner's column: cells z-2 .. z+3 after each push
-  LRec<NV> w0, w1, w2, w3, w4, w5;
+  // owner registers: r0..r3 = cells z-1 .. z+2 at the top of iteration z;
+  // the ring holds cell c in slot (c & 1)
+  LRec<NV> r0, r1, r2, r3;
   double Fzp[NV];
+  bool zprev = false;  // face z - 1/2 needs the nonlinear flux
   double upre[NV], hpre[NV];
   if (owner) {
     double u[NV];
-    load_xyz<NV>(a.Uk, g, gx, gy, z0 - 3, u);
-    make_lrec<NV>(u, ph, w0);
-    load_xyz<NV>(a.Uk, g, gx, gy, z0 - 2, u);
-    make_lrec<NV>(u, ph, w1);
-    load_xyz<NV>(a.Uk, g, gx, gy, z0 - 1, u);
-    make_lrec<NV>(u, ph, w2);
-    load_xyz<NV>(a.Uk, g, gx, gy, z0, u);
-    make_lrec<NV>(u, ph, w3);
-    load_xyz<NV>(a.Uk, g, gx, gy, z0 + 1, u);
-    make_lrec<NV>(u, ph, w4);
-    load_xyz<NV>(a.Uk, g, gx, gy, z0 + 2, u);
-    make_lrec<NV>(u, ph, w5);
-    // face z0 - 1/2 (cells z0-3 .. z0+2)
-    const WinSrc<NV> src{w0, w1, w2, w3, w4, w5};
-    const unsigned m = face_linear_l<NV, 2>(src, ph, ph.eps_thr[2], lfz, Fzp);
-    if (m) {
-      double dF[NV];
-      lean_correction<NV, 2>(src, m, ph, lfz, dF);
+    LRec<NV> c0, c1;
+    load_col<NV>(a.Uk, g, ocol, z0 - 3, u);
+    make_lrec<NV>(u, ph, c0);
+    load_col<NV>(a.Uk, g, ocol, z0 - 2, u);
+    make_lrec<NV>(u, ph, c1);
+    load_col<NV>(a.Uk, g, ocol, z0 - 1, u);
+    make_lrec<NV>(u, ph, r0);
+    load_col<NV>(a.Uk, g, ocol, z0, u);
+    make_lrec<NV>(u, ph, r1);
+    load_col<NV>(a.Uk, g, ocol, z0 + 1, u);
+    make_lrec<NV>(u, ph, r2);
+    load_col<NV>(a.Uk, g, ocol, z0 + 2, u);
+    make_lrec<NV>(u, ph, r3);
+    // ring: cells z0-3 and z0-2
+    const int s3 = (z0 - 3) & 1, s2 = (z0 - 2) & 1;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fzp[v] += dF[v];
+    for (int v = 0; v < NV; ++v) {
+      swin[s3][v][t] = c0.U[v];
+      swin[s2][v][t] = c1.U[v];
     }
-    load_xyz<NV>(a.Uk, g, gx, gy, z0 + 3, upre);
+    swin[s3][NV][t] = c0.p;
+    swin[s3][NV + 1][t] = c0.c;
+    swin[s3][NV + 2][t] = c0.iw;
+    swin[s2][NV][t] = c1.p;
+    swin[s2][NV + 1][t] = c1.c;
+    swin[s2][NV + 2][t] = c1.iw;
+    // face z0 - 1/2 (cells z0-3 .. z0+2): window c0, c1, r0, r1, r2, r3
+    const WinSrc<NV> src{c0, c1, r0, r1, r2, r3};
+    zprev = face_linear_l<NV, 2, SPLIT, HYB>(src, ph, ph.eps_thr[2], lfz, Fzp) != 0u;
+    load_col<NV>(a.Uk, g, ocol, z0 + 3, upre);
   }
-  if (t < NHALO) load_xyz<NV>(a.Uk, g, x0 + hc, y0 + hr, z0, hpre);
+  if (t < NHALO) load_col<NV>(a.Uk, g, hcol, z0, hpre);
 
   for (int z = z0; z < z1; ++z) {
     if (owner) {
-      // push cell z+3; window becomes z-2 .. z+3
-      w0 = w1;
-      w1 = w2;
-      w2 = w3;
-      w3 = w4;
-      w4 = w5;
-      make_lrec<NV>(upre, ph, w5);
-      if (z + 1 < z1) load_xyz<NV>(a.Uk, g, gx, gy, z + 4, upre);
-      lds_put<NV>(srec, lds_own, w2);  // cell z
+      // retire cell z-1 into the ring (overwrites cell z-3), then shift:
+      // registers become cells z .. z+3
+      const int sl = (z - 1) & 1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) swin[sl][v][t] = r0.U[v];
+      swin[sl][NV][t] = r0.p;
+      swin[sl][NV + 1][t] = r0.c;
+      swin[sl][NV + 2][t] = r0.iw;
+      r0 = r1;
+      r1 = r2;
+      r2 = r3;
+      make_lrec<NV>(upre, ph, r3);
+      if (z + 1 < z1) load_col<NV>(a.Uk, g, ocol, z + 4, upre);
+      lds_put<NV>(srec, lds_own, r0);  // cell z
     }
     if (t < NHALO) {
-      LRec<NV> hr_;
-      make_lrec<NV>(hpre, ph, hr_);
-      lds_put<NV>(srec, lds_halo, hr_);
-      if (z + 1 < z1) load_xyz<NV>(a.Uk, g, x0 + hc, y0 + hr, z + 1, hpre);
+      LRec<NV> hrec;
+      make_lrec<NV>(hpre, ph, hrec);
+      lds_put<NV>(srec, lds_halo, hrec);
+      if (z + 1 < z1) load_col<NV>(a.Uk, g, hcol, z + 1, hpre);
     }
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
@@ -485,13 +544,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       const int base = (row + 3) * FP_X + fx;
       const LdsSrc<NV> src{srec, base, 1};
       double F[NV];
-      const unsigned m = face_linear_l<NV, 0>(src, ph, ph.eps_thr[0], lfx, F);
-      if (m) {
-        double dF[NV];
-        lean_correction<NV, 0>(src, m, ph, lfx, dF);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] += dF[v];
-      }
+      sgx[t] = face_linear_l<NV, 0, SPLIT, HYB>(src, ph, ph.eps_thr[0], lfx, F) != 0u;
 #pragma unroll
       for (int v = 0; v < NV; ++v) sfx[v][t] = F[v];
     }
@@ -502,52 +555,141 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       const int base = fy * FP_X + col + 3;
       const LdsSrc<NV> src{srec, base, FP_X};
       double F[NV];
-      const unsigned m = face_linear_l<NV, 1>(src, ph, ph.eps_thr[1], lfy, F);
-      if (m) {
-        double dF[NV];
-        lean_correction<NV, 1>(src, m, ph, lfy, dF);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] += dF[v];
-      }
+      sgy[t] = face_linear_l<NV, 1, SPLIT, HYB>(src, ph, ph.eps_thr[1], lfy, F) != 0u;
 #pragma unroll
       for (int v = 0; v < NV; ++v) sfy[v][t] = F[v];
     }
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
-    double Fz[NV];
     if (owner) {
-      // z face z + 1/2 from the register window
-      const WinSrc<NV> src{w0, w1, w2, w3, w4, w5};
-      const unsigned m = face_linear_l<NV, 2>(src, ph, ph.eps_thr[2], lfz, Fz);
-      if (m) {
-        double dF[NV];
-        lean_correction<NV, 2>(src, m, ph, lfz, dF);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Fz[v] += dF[v];
-      }
-    }
-    if (valid) {
-      const long long off = gx + (long long)gy * g.stride[1] + (long long)z * g.stride[2];
+      // z face z + 1/2: cells z-2, z-1 (ring), z .. z+3 (registers)
+      double Fz[NV];
+      const ZSrc<NV> src{swin, (z - 2) & 1, (z - 1) & 1, t, r0, r1, r2, r3};
+      const bool zcur = face_linear_l<NV, 2, SPLIT, HYB>(src, ph, ph.eps_thr[2], lfz, Fz) != 0u;
       const int ix = oy * (FT_X + 1) + ox;
       const int iy = oy * FT_X + ox;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double dU = ((sfx[v][ix] - sfx[v][ix + 1]) + (sfy[v][iy] - sfy[v][iy + FT_X]) +
-                           (Fzp[v] - Fz[v])) * ph.inv_dx;
-        if (OUT == OUT_RK) {
-          double r = a.rk_b * (w2.U[v] + dt * dU);
-          if (a.rk_a != 0.0) r += a.rk_a * a.Un[v * g.ncell + off];
-          a.out[v * g.ncell + off] = r;
-        } else {
-          a.out[v * g.ncell + off] = dU;
+      const long long off = oout + (long long)z * g.stride[2];
+      // faces of this cell that need the nonlinear flux: x-, x+, y-, y+, z-, z+
+      unsigned cm = 0;
+      if (valid) {
+        cm = (sgx[ix] ? 1u : 0u) | (sgx[ix + 1] ? 2u : 0u) | (sgy[iy] ? 4u : 0u) |
+             (sgy[iy + FT_X] ? 8u : 0u) | (zprev ? 16u : 0u) | (zcur ? 32u : 0u);
+      }
+      zprev = zcur;
+      // wave-aggregated append to the correction list
+      const unsigned long long ball = __ballot(cm != 0u);
+      if (ball) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)ball) - 1;
+        unsigned int basei = 0;
+        if (lane == leader) basei = atomicAdd(a.list_n, (unsigned int)__popcll(ball));
+        basei = __shfl(basei, leader, 64);
+        if (cm) {
+          const unsigned int rank = __popcll(ball & ((1ull << lane) - 1ull));
+          a.list[basei + rank] = ((unsigned long long)off << 8) | cm;
         }
       }
-    }
-    if (owner) {
+      if (valid) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double dU = ((sfx[v][ix] - sfx[v][ix + 1]) + (sfy[v][iy] - sfy[v][iy + FT_X]) +
+                             (Fzp[v] - Fz[v])) * ph.inv_dx;
+          if (OUT == OUT_RK) {
+            double r = a.rk_b * (r0.U[v] + dt * dU);
+            if (a.rk_a != 0.0) r += a.rk_a * a.Un[v * g.ncell + off];
+            a.out[v * g.ncell + off] = r;
+          } else {
+            a.out[v * g.ncell + off] = dU;
+          }
+        }
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fzp[v] = Fz[v];
     }
   }
+}
+
+// Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
+// the face below the cell, side 1 the face above.  Returns the change of the
+// face flux (WENO minus linear, Eq.(33) per field).
+template <int NV, int DIR, int SPLIT, int HYB>
+__device__ __forceinline__ void face_delta(const double* U, const KGrid& g, const KPhys& ph,
+                                           const unsigned long long* lfb, int x, int y, int z,
+                                           int side, double (&dF)[NV]) {
+  struct Src {
+    const double* U;
+    const KGrid* g;
+    const KPhys* ph;
+    int c[3];
+    __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
+      double u[NV];
+      bool flip;
+      const int k = ghost_clamped(c[DIR] + m, g->n[DIR], g->bc_lo[DIR], g->bc_hi[DIR], flip);
+      int p[3] = {c[0], c[1], c[2]};
+      p[DIR] = k;
+      const long long off = p[0] + (long long)p[1] * g->stride[1] + (long long)p[2] * g->stride[2];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = U[v * g->ncell + off];
+      if (flip) u[1 + DIR] = -u[1 + DIR];
+      make_lrec<NV>(u, *ph, r);
+    }
+  } src{U, &g, &ph, {x, y, z}};
+  // face below the cell: stencil starts 3 cells below; face above: 2 below
+  src.c[DIR] += side ? -2 : -3;
+  double Flin[NV];
+  const unsigned mask =
+      face_linear_l<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin);
+  if (mask) {
+    lean_correction<NV, DIR>(src, mask, ph, lfb, dF);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+  }
+}
+
+// One thread per listed cell: add the nonlinear part of the flux of its
+// flagged faces, in the fixed order x-, x+, y-, y+, z-, z+, to the output
+// (scaled by rk_b dt for a stage, 1 for dU/dt).  Each cell is owned by one
+// thread, so the result does not depend on scheduling.
+template <int OUT, int SPLIT, int HYB>
+__global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
+  constexpr int NV = 5;
+  double scale = 1.0;
+  if (OUT == OUT_RK) {
+    const double dt = a.ctl->dt;
+    if (!(dt > 0.0)) return;
+    scale = a.rk_b * dt;
+  }
+  const unsigned int n = *a.list_n;
+  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const unsigned long long e = a.list[i];
+    const long long off = (long long)(e >> 8);
+    const unsigned cm = (unsigned)(e & 0xffu);
+    const int x = (int)(off % g.n[0]);
+    const int y = (int)((off / g.n[0]) % g.n[1]);
+    const int z = (int)(off / g.stride[2]);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int f = 0; f < 6; ++f) {
+      if (!((cm >> f) & 1u)) continue;
+      const int dir = f >> 1, side = f & 1;
+      double dF[NV];
+      if (dir == 0) face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, z, side, dF);
+      else if (dir == 1) face_delta<NV, 1, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, z, side, dF);
+      else face_delta<NV, 2, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[2], x, y, z, side, dF);
+      // dU = -(F_{+} - F_{-}) / dx: the face below adds, the face above subtracts
+      const double sg = side ? -1.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sg * dF[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.out[v * g.ncell + off] += scale * (acc[v] * ph.inv_dx);
+  }
+}
+
+__global__ void reset_list_kernel(unsigned int* list_n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *list_n = 0u;
 }
 
 }  // namespace wl2
