@@ -31,6 +31,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "fused3d_rk_turbulence256.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the stage kernel from the committed rocprofv3
+    counter summary, or None if it is missing or the kernel sources changed
+    since the counters were taken."""
+    try:
+        from paper_1908_02464_amd.rocprof_summary import source_hash
+        txt = open(PROFILE).read()
+        info = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        if info.get("source_hash") != source_hash():
+            return None, "stale"
+        return info.get("traffic_bytes_per_launch"), info.get("source_hash")
+    except (OSError, ValueError, IndexError, KeyError):
+        return None, "missing"
+
+
 def cpu_baseline(U0, dx, min_seconds=10.0):
     """The oracle as it stands, one thread, on a 256x256x16 slab of the same
     initial field (x, y periodic as in the workload; z transmissive)."""
@@ -128,6 +146,9 @@ def main():
                    "sweep_x_accum": 3.0, "sweep_y_write": 2.0, "sweep_z_accum": 3.0}
     dom_bytes = role_arrays.get(dom, 2.0) * arr
     achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
+    traffic, traffic_src = (None, "n/a")
+    if dom == "fused3d_rk":
+        traffic, traffic_src = measured_traffic()
     # the method's own bytes per cell-stage: 8/3 state arrays (read U^(k), U^n,
     # write U^(k+1); stage 1 reads only U^n)
     path_bytes = 8.0 / 3.0 * nvar * 8
@@ -184,7 +205,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (round(traffic) if traffic else None),
+            "traffic_source": traffic_src,
             "avg_launch_ms": round(avg_ms, 4),
             "launches": dom_n,
             "algorithmic_bytes_per_launch": int(dom_bytes),

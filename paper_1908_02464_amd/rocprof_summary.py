@@ -1,0 +1,103 @@
+"""Summarize rocprofv3 CSV output for one kernel into a short text file.
+
+Usage (after a kernel-trace run and two counter runs of the same command):
+  python -m paper_1908_02464_amd.rocprof_summary --kernel fused3d_kernel \
+      --trace DIR_TRACE --fetch DIR_FETCH --write DIR_WRITE \
+      --command "the rocprofv3 command line" --out profiles/NAME.txt
+
+FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are scaled by what the same
+counters read for the device copy of one 655360 KiB state array in the same
+runs (bench.py --copy-calibration), so the reported traffic is in bytes.
+The summary records a hash of the kernel sources so that stale counter
+numbers are recognised.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+COPY_KIB = 655360.0  # one 256^3 x 5 FP64 state array
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(d, pattern):
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"{pattern} under {d}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def trace_stats(d, kernel):
+    rows = _rows(d, "*kernel_stats.csv")
+    out = {}
+    for r in rows:
+        if kernel in r["Name"]:
+            out[r["Name"]] = {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                              "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"]),
+                              "pct": float(r["Percentage"])}
+    return out
+
+
+def counter(d, kernel, name):
+    rows = _rows(d, "*counter_collection.csv")
+    vals = [float(r["Counter_Value"]) for r in rows
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == name]
+    cal = [float(r["Counter_Value"]) for r in rows
+           if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == name
+           and int(r["Grid_Size"]) > 1000]
+    return vals, cal
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--workload", default="3D Euler turbulence 256^3 periodic, FP64")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    info = {"kernel": a.kernel, "workload": a.workload, "command": a.command,
+            "source_hash": source_hash(), "trace": trace_stats(a.trace, a.kernel)}
+    if a.fetch and a.write:
+        fv, fc = counter(a.fetch, a.kernel, "FETCH_SIZE")
+        wv, wc = counter(a.write, a.kernel, "WRITE_SIZE")
+        ff = COPY_KIB / statistics.mean(fc) if fc else None
+        wf = COPY_KIB / statistics.mean(wc) if wc else None
+        info["counters"] = {
+            "FETCH_SIZE_KiB_per_dispatch": statistics.mean(fv),
+            "WRITE_SIZE_KiB_per_dispatch": statistics.mean(wv),
+            "dispatches": len(fv),
+            "copy_calibration": {"FETCH_SIZE_KiB": statistics.mean(fc) if fc else None,
+                                 "WRITE_SIZE_KiB": statistics.mean(wc) if wc else None,
+                                 "true_KiB": COPY_KIB, "fetch_factor": ff, "write_factor": wf},
+        }
+        if ff and wf:
+            info["traffic_bytes_per_launch"] = (statistics.mean(fv) * ff +
+                                                statistics.mean(wv) * wf) * 1024.0
+    lines = ["# rocprofv3 summary: " + a.kernel, "",
+             "command: " + a.command, "",
+             "```json", json.dumps(info, indent=1), "```", ""]
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
