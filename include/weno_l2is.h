@@ -165,6 +165,57 @@ int weno_l2is_timing_read(weno_l2is_ctx *ctx, int cap, char *names,
 /* Free the context and its scratch (synchronizes its stream first). */
 void weno_l2is_destroy(weno_l2is_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched and served form: many independent 1D/2D runs of uneven sizes
+ * advanced together.  Each step is one replay of a captured hipGraph whose
+ * persistent kernels walk ragged per-phase work tables over all admitted
+ * runs; every run keeps its own CFL dt, clock (stopping exactly at its t_end)
+ * and status.  A run's result is bit-identical to running it alone through
+ * weno_l2is_advance (same device code, same operation order).
+ * The engine allocates `hbm_budget_bytes` once at creation and sub-allocates
+ * runs from it: admission fails with WL2_E_BUDGET when a run's footprint
+ * (3 state arrays, plus a partial-sum array in 2D) does not fit or all
+ * `max_slots` slots are taken.  No device allocation happens while serving.
+ * LF splitting (WL2_SPLIT_LF) and 3D grids are not supported in a batch
+ * (WL2_E_PARAM / WL2_E_SHAPE).
+ * All calls are asynchronous on the engine's stream unless noted.
+ * ------------------------------------------------------------------------ */
+typedef struct weno_l2is_batch weno_l2is_batch;
+
+int weno_l2is_batch_create(size_t hbm_budget_bytes, int max_slots,
+                           void *hip_stream, weno_l2is_batch **out);
+
+/* Admit a run: copies U0 (host pointer if u0_on_host, else device pointer,
+ * layout as everywhere) into engine memory, clock 0, target t_end > 0.
+ * Returns its slot in *slot.  Footprint in bytes in *bytes (may be NULL). */
+int weno_l2is_batch_admit(weno_l2is_batch *b, int nx, int ny, int nz,
+                          double dx, double gamma, const weno_l2is_params *p,
+                          const double *U0, int u0_on_host, double t_end,
+                          int *slot, size_t *bytes);
+
+/* Enqueue n_steps batched SSP-RK3 steps of all admitted runs, then a
+ * snapshot of every run's clock and status for weno_l2is_batch_poll. */
+int weno_l2is_batch_advance(weno_l2is_batch *b, int n_steps);
+
+/* Non-blocking: if the latest snapshot has landed, store up to `cap` slots
+ * that reached t_end (or stopped on a non-physical state) and were not
+ * reported before; *n_done = number stored (0 if nothing new or the snapshot
+ * is still in flight). */
+int weno_l2is_batch_poll(weno_l2is_batch *b, int *done_slots, int cap,
+                         int *n_done);
+
+/* Synchronize, copy the run's state to U_out (host if out_on_host, else
+ * device), report its time and status bits, and free the slot and its
+ * memory.  Returns WL2_E_SLOT for a slot not in use. */
+int weno_l2is_batch_fetch(weno_l2is_batch *b, int slot, double *U_out,
+                          int out_on_host, double *t_out, unsigned *status);
+
+/* Bytes of the budget in use and number of admitted runs. */
+int weno_l2is_batch_usage(weno_l2is_batch *b, size_t *used_bytes,
+                          int *active);
+
+void weno_l2is_batch_destroy(weno_l2is_batch *b);
+
 /* Static string for a return code. */
 const char *weno_l2is_strerror(int code);
 

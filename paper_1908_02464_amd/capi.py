@@ -71,6 +71,14 @@ def lib():
         "weno_l2is_timing_read": (ip, [vp, ip, C.c_char_p, C.POINTER(dp), C.POINTER(C.c_longlong),
                                        C.POINTER(ip)]),
         "weno_l2is_destroy": (None, [vp]),
+        "weno_l2is_batch_create": (ip, [C.c_size_t, ip, vp, C.POINTER(vp)]),
+        "weno_l2is_batch_admit": (ip, [vp, ip, ip, ip, dp, dp, pp, vp, ip, dp,
+                                       C.POINTER(ip), C.POINTER(C.c_size_t)]),
+        "weno_l2is_batch_advance": (ip, [vp, ip]),
+        "weno_l2is_batch_poll": (ip, [vp, C.POINTER(ip), ip, C.POINTER(ip)]),
+        "weno_l2is_batch_fetch": (ip, [vp, ip, vp, ip, C.POINTER(dp), C.POINTER(C.c_uint)]),
+        "weno_l2is_batch_usage": (ip, [vp, C.POINTER(C.c_size_t), C.POINTER(ip)]),
+        "weno_l2is_batch_destroy": (None, [vp]),
         "weno_l2is_strerror": (C.c_char_p, [ip]),
     }
     for name, (res, args) in sig.items():
@@ -199,6 +207,79 @@ class Context:
     def close(self):
         if getattr(self, "h", None):
             lib().weno_l2is_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns a weno_l2is_batch engine (batched / served runs, 1D and 2D)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 1024,
+                 stream: torch.cuda.Stream | None = None):
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = C.c_void_p()
+        _chk(lib().weno_l2is_batch_create(int(budget_bytes), int(max_slots),
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+             "batch_create")
+        self.h = h
+        self.meta = {}
+
+    def admit(self, U0, nx: int, ny: int, nz: int, dx: float, t_end: float,
+              gamma: float = 1.4, params: Params | None = None):
+        """Admit a run; U0 is a host numpy float64 array or a CUDA tensor.
+        Returns the slot, or None when the budget or the slot table is full."""
+        import numpy as np
+        p = params if params is not None else params_default(nx, ny, nz, dx)
+        slot, nbytes = C.c_int(-1), C.c_size_t(0)
+        if isinstance(U0, torch.Tensor):
+            ptr, host = _ptr(U0, U0.numel()), 0
+        else:
+            U0 = np.ascontiguousarray(U0, dtype=np.float64)
+            ptr, host = U0.ctypes.data, 1
+        rc = lib().weno_l2is_batch_admit(self.h, nx, ny, nz, dx, gamma, C.byref(p), C.c_void_p(ptr),
+                                         host, float(t_end), C.byref(slot), C.byref(nbytes))
+        if rc == E_BUDGET:
+            return None
+        _chk(rc, "batch_admit")
+        self.meta[slot.value] = (nx, ny, nz)
+        return slot.value
+
+    def advance(self, n_steps: int = 1):
+        _chk(lib().weno_l2is_batch_advance(self.h, int(n_steps)), "batch_advance")
+
+    def poll(self, cap: int = 4096):
+        arr = (C.c_int * cap)()
+        n = C.c_int(0)
+        _chk(lib().weno_l2is_batch_poll(self.h, arr, cap, C.byref(n)), "batch_poll")
+        return [arr[i] for i in range(n.value)]
+
+    def fetch(self, slot: int):
+        """Copy the run's state to a host array, free the slot.
+        Returns (U, t, status)."""
+        import numpy as np
+        if slot not in self.meta:
+            raise WenoL2ISError(f"weno_l2is_batch_fetch: slot {slot} holds no run")
+        nx, ny, nz = self.meta.pop(slot)
+        dim, nvar, ncell = grid_dims(nx, ny, nz)
+        U = np.empty((nvar, nz, ny, nx))
+        t, st = C.c_double(0.0), C.c_uint(0)
+        _chk(lib().weno_l2is_batch_fetch(self.h, int(slot), C.c_void_p(U.ctypes.data), 1,
+                                         C.byref(t), C.byref(st)), "batch_fetch")
+        return U, t.value, st.value
+
+    def usage(self):
+        used, act = C.c_size_t(0), C.c_int(0)
+        _chk(lib().weno_l2is_batch_usage(self.h, C.byref(used), C.byref(act)), "batch_usage")
+        return used.value, act.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().weno_l2is_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
 
 // dt = cfl dx / smax (or a fixed dt), clipped to the device clock when
 // use_clock; resets the running maximum for the next reduction.
-__global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock) {
+[[maybe_unused]] static __global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / __longlong_as_double((long long)ctl->smax_bits);
   if (use_clock) {
@@ -88,13 +88,13 @@ __global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed,
 }
 
 // Program the device clock target (enqueued, no host synchronisation).
-__global__ void set_t_end_kernel(StepCtl* ctl, double t_end) {
+[[maybe_unused]] static __global__ void set_t_end_kernel(StepCtl* ctl, double t_end) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t_end = t_end;
 }
 
 // Global LF speeds along every active direction: max over cells of
 // |u_d - c|, |u_d|, |u_d + c| (fields u-c, entropy/shear, u+c).
-__global__ void lf_reset_kernel(StepCtl* ctl) {
+[[maybe_unused]] static __global__ void lf_reset_kernel(StepCtl* ctl) {
   if (threadIdx.x < 15) (&ctl->lf_bits[0][0])[threadIdx.x] = 0ull;
 }
 

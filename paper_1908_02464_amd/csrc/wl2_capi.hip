@@ -13,7 +13,8 @@
 
 #include "../../include/weno_l2is.h"
 #include "wl2_aux.hpp"
-#include "wl2_fused.hpp"
+#include "wl2_desc.hpp"
+#include "wl2_fused_launch.hpp"
 #include "wl2_kernels.hpp"
 
 using namespace wl2;
@@ -68,10 +69,10 @@ struct TimedLaunch {
     }
     slot = (int)(2 * c->ev_used.size());
     c->ev_used.emplace_back(id, slot);
-    hipEventRecord(c->ev_pool[slot], c->stream);
+    (void)hipEventRecord(c->ev_pool[slot], c->stream);
   }
   ~TimedLaunch() {
-    if (slot >= 0) hipEventRecord(c->ev_pool[slot + 1], c->stream);
+    if (slot >= 0) (void)hipEventRecord(c->ev_pool[slot + 1], c->stream);
   }
 };
 
@@ -84,54 +85,10 @@ const char* sweep_name() {
 }
 
 int validate(int nx, int ny, int nz, double dx, double gamma, const weno_l2is_params* p) {
-  if (!p) return WL2_E_NULL;
-  if (nx < 1 || ny < 1 || nz < 1) return WL2_E_SHAPE;
-  if (nz > 1 && ny < 2) return WL2_E_SHAPE;
-  if ((long long)nx * ny * nz > (1LL << 40)) return WL2_E_SHAPE;
-  if (!(dx > 0.0) || !std::isfinite(dx) || !(gamma > 1.0) || !std::isfinite(gamma))
-    return WL2_E_PARAM;
-  if (!(p->cfl > 0.0) || !(p->c_reg >= 0.0) || !(p->eps_weno >= 0.0) || !(p->thr_C >= 0.0) ||
-      p->thr_alpha < 0 || p->thr_alpha > 64)
-    return WL2_E_PARAM;
-  if (p->split < 0 || p->split > 2 || p->hybrid < 0 || p->hybrid > 3) return WL2_E_PARAM;
-  const int dim = nz > 1 ? 3 : (ny > 1 ? 2 : 1);
-  const int n[3] = {nx, ny, nz};
-  for (int d = 0; d < dim; ++d) {
-    const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return WL2_E_BC;
-    if ((lo == WL2_BC_PERIODIC) != (hi == WL2_BC_PERIODIC)) return WL2_E_BC;
-    if ((lo == WL2_BC_REFLECTIVE || hi == WL2_BC_REFLECTIVE) && n[d] < 3) return WL2_E_BC;
-    if (!(p->thr_L[d] > 0.0)) return WL2_E_PARAM;
-  }
-  return WL2_OK;
+  return validate_grid(nx, ny, nz, dx, gamma, p);
 }
 
-void fill_desc(weno_l2is_ctx* c) {
-  for (int d = 0; d < 3; ++d) {
-    c->g.n[d] = c->n[d];
-    c->g.bc_lo[d] = c->p.bc[2 * d];
-    c->g.bc_hi[d] = c->p.bc[2 * d + 1];
-  }
-  c->g.stride[0] = 1;
-  c->g.stride[1] = c->n[0];
-  c->g.stride[2] = (long long)c->n[0] * c->n[1];
-  c->g.ncell = c->ncell;
-  c->ph.gamma = c->gamma;
-  c->ph.gm1 = c->gamma - 1.0;
-  c->ph.dx = c->dx;
-  c->ph.inv_dx = 1.0 / c->dx;
-  c->ph.cfl = c->p.cfl;
-  c->ph.c_reg = c->p.c_reg;
-  c->ph.eps_w = c->p.eps_weno;
-  for (int d = 0; d < 3; ++d) {
-    double e = c->p.thr_C;
-    const double r = c->dx / c->p.thr_L[d];
-    for (int k = 0; k < c->p.thr_alpha; ++k) e *= r;  // C (dx/L)^alpha, Eq.(35)
-    c->ph.eps_thr[d] = (d < c->dim) ? e : 0.0;
-  }
-  c->ph.split = c->p.split;
-  c->ph.hybrid = c->p.hybrid;
-}
+void fill_desc(weno_l2is_ctx* c) { fill_grid_desc(c->n, c->dim, c->dx, c->gamma, c->p, c->g, c->ph); }
 
 int hip_err(hipError_t e) { return e == hipSuccess ? WL2_OK : WL2_E_HIP; }
 
@@ -222,58 +179,33 @@ int fused_zchunk(const weno_l2is_ctx* c) {
 
 hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
                         const double* Un, double ra, double rb) {
-  FusedArgs a;
-  a.Uk = Uk;
-  a.out = out;
-  a.Un = Un;
-  a.ctl = c->ctl;
-  a.rk_a = ra;
-  a.rk_b = rb;
-  a.zc = fused_zchunk(c);
-  a.list = c->list;
-  a.list_n = &c->ctl->list_n;
-  a.tiles_x = (c->n[0] + FT_X - 1) / FT_X;
-  a.tiles_y = (c->n[1] + FT_Y - 1) / FT_Y;
-  const long long nzc = (c->n[2] + a.zc - 1) / a.zc;
-  const long long blocks = (long long)a.tiles_x * a.tiles_y * nzc;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const dim3 gr((unsigned)blocks), bl(FT_THREADS);
+  FusedLaunch L;
+  L.Uk = Uk;
+  L.out = out;
+  L.Un = Un;
+  L.ctl = c->ctl;
+  L.list = c->list;
+  L.rk_a = ra;
+  L.rk_b = rb;
+  L.out_kind = out_kind;
+  L.zc = fused_zchunk(c);
+  L.wpe = c->wpe;
   // compile-time fast path for the paper's 1D/3D defaults: LLF splitting,
   // per-field switch
-  const bool fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
-#define WL2_FUSED(O, W, S, H) \
-  hipLaunchKernelGGL((fused3d_kernel<O, W, S, H>), gr, bl, 0, c->stream, a, c->g, c->ph)
-  hipLaunchKernelGGL(reset_list_kernel, dim3(1), dim3(64), 0, c->stream, a.list_n);
+  L.fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
+  for (int d = 0; d < 3; ++d) L.n[d] = c->n[d];
+  L.g = c->g;
+  L.ph = c->ph;
+  L.stream = c->stream;
+  hipError_t e = fused3d_reset(L);
+  if (e != hipSuccess) return e;
   {
-  TimedLaunch tl(c, out_kind == OUT_RK ? "fused3d_rk" : "fused3d_rhs");
-  if (out_kind == OUT_RK) {
-    if (c->wpe == 2) {
-      if (fast) WL2_FUSED(OUT_RK, 2, 0, 0); else WL2_FUSED(OUT_RK, 2, -1, -1);
-    } else {
-      if (fast) WL2_FUSED(OUT_RK, 1, 0, 0); else WL2_FUSED(OUT_RK, 1, -1, -1);
-    }
-  } else {
-    if (c->wpe == 2) {
-      if (fast) WL2_FUSED(OUT_WRITE, 2, 0, 0); else WL2_FUSED(OUT_WRITE, 2, -1, -1);
-    } else {
-      if (fast) WL2_FUSED(OUT_WRITE, 1, 0, 0); else WL2_FUSED(OUT_WRITE, 1, -1, -1);
-    }
+    TimedLaunch tl(c, out_kind == OUT_RK ? "fused3d_rk" : "fused3d_rhs");
+    if ((e = fused3d_main(L)) != hipSuccess) return e;
   }
-  }
-#undef WL2_FUSED
   // nonlinear corrections of the listed cells (an empty list exits at once)
-  {
-    TimedLaunch tl(c, "weno_fix3d");
-    const dim3 fg(1024), fb(128);
-#define WL2_FIX(O, S, H) hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H>), fg, fb, 0, c->stream, a, c->g, c->ph)
-    if (out_kind == OUT_RK) {
-      if (fast) WL2_FIX(OUT_RK, 0, 0); else WL2_FIX(OUT_RK, -1, -1);
-    } else {
-      if (fast) WL2_FIX(OUT_WRITE, 0, 0); else WL2_FIX(OUT_WRITE, -1, -1);
-    }
-#undef WL2_FIX
-  }
-  return hipGetLastError();
+  TimedLaunch tl(c, "weno_fix3d");
+  return fused3d_fix(L);
 }
 
 // dU/dt of the state Uk into out (WRITE then ACCUM over directions).
@@ -367,11 +299,11 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
     ok = hipMalloc(&c->list, sizeof(unsigned long long) * (size_t)c->ncell) == hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
-    hipFree(c->U1);
-    hipFree(c->U2);
-    hipFree(c->acc);
-    hipFree(c->list);
-    hipFree(c->ctl);
+    (void)hipFree(c->U1);
+    (void)hipFree(c->U2);
+    (void)hipFree(c->acc);
+    (void)hipFree(c->list);
+    (void)hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
     return WL2_E_NOMEM;
@@ -382,13 +314,13 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
 
 void weno_l2is_destroy(weno_l2is_ctx* c) {
   if (!c) return;
-  hipStreamSynchronize(c->stream);
-  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-  hipFree(c->U1);
-  hipFree(c->U2);
-  hipFree(c->acc);
-  hipFree(c->list);
-  hipFree(c->ctl);
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  (void)hipFree(c->U1);
+  (void)hipFree(c->U2);
+  (void)hipFree(c->acc);
+  (void)hipFree(c->list);
+  (void)hipFree(c->ctl);
   delete c;
 }
 

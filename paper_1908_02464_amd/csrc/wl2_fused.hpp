@@ -18,10 +18,11 @@
 // their halos in that XCD's L2.
 #pragma once
 #include "wl2_device.hpp"
+#include "wl2_fused_launch.hpp"
 
 namespace wl2 {
 
-constexpr int FT_X = 16, FT_Y = 15, FT_THREADS = 256;
+constexpr int FT_THREADS = 256;
 constexpr int FT_OWN = FT_X * FT_Y;              // 240 column owners
 constexpr int FP_X = FT_X + 6, FP_Y = FT_Y + 6;  // LDS plane pitch (with halo)
 constexpr int FP_N = FP_X * FP_Y;
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
   }
 }
 
-__global__ void reset_list_kernel(unsigned int* list_n) {
+[[maybe_unused]] static __global__ void reset_list_kernel(unsigned int* list_n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *list_n = 0u;
 }
 

@@ -1,0 +1,38 @@
+// Launch interface of the fused 3D stage kernels, which live in a translation
+// unit of their own (wl2_fused3d.hip) so that they can be compiled with
+// cross-statement FMA contraction while the sweep kernels keep contraction
+// inside single expressions (see build.py).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "wl2_device.hpp"
+
+namespace wl2 {
+
+// Column tile of the fused kernel: FT_X x FT_Y cells per workgroup in x, y.
+constexpr int FT_X = 16, FT_Y = 15;
+
+struct FusedLaunch {
+  const double* Uk;
+  double* out;
+  const double* Un;
+  StepCtl* ctl;
+  unsigned long long* list;
+  double rk_a, rk_b;
+  int out_kind;  // OUT_WRITE or OUT_RK
+  int zc;        // z planes per workgroup
+  int wpe;       // 1 or 2 waves per SIMD
+  int fast;      // LLF splitting with the per-field switch (compile-time path)
+  int n[3];
+  KGrid g;
+  KPhys ph;
+  hipStream_t stream;
+};
+
+// The three launches of one fused stage, in stream order: clear the
+// correction list, the fused stage kernel, the nonlinear corrections.
+hipError_t fused3d_reset(const FusedLaunch& L);
+hipError_t fused3d_main(const FusedLaunch& L);
+hipError_t fused3d_fix(const FusedLaunch& L);
+
+}  // namespace wl2

@@ -49,11 +49,12 @@ __device__ __forceinline__ void sweep_map(long long gid, const KGrid& g, int nse
   }
 }
 
+// Work of one thread: segment `gid` (0 <= gid < nseg * lines) of the sweep
+// along DIR.  Shared by the single-grid kernel and the batched kernel, so a
+// grid gets the same bits whether it runs alone or in a batch.
 template <int NV, int DIR, int S, int OUT>
-__global__ __launch_bounds__(SWEEP_BLOCK) void sweep_kernel(SweepArgs a, KGrid g, KPhys ph,
-                                                            int nseg, long long nthreads) {
-  const long long gid = (long long)blockIdx.x * SWEEP_BLOCK + threadIdx.x;
-  if (gid >= nthreads) return;
+__device__ __forceinline__ void sweep_body(const SweepArgs& a, const KGrid& g, const KPhys& ph,
+                                           int nseg, long long gid) {
   long long base;
   int seg;
   sweep_map<DIR>(gid, g, nseg, base, seg);
@@ -149,6 +150,14 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void sweep_kernel(SweepArgs a, KGrid g
       for (int v = 0; v < NV; ++v) a.out[v * g.ncell + off] += scale * (dF[v] * ph.inv_dx);
     }
   }
+}
+
+template <int NV, int DIR, int S, int OUT>
+__global__ __launch_bounds__(SWEEP_BLOCK) void sweep_kernel(SweepArgs a, KGrid g, KPhys ph,
+                                                            int nseg, long long nthreads) {
+  const long long gid = (long long)blockIdx.x * SWEEP_BLOCK + threadIdx.x;
+  if (gid >= nthreads) return;
+  sweep_body<NV, DIR, S, OUT>(a, g, ph, nseg, gid);
 }
 
 }  // namespace wl2

@@ -25,12 +25,18 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 COPY_KIB = 655360.0  # one 256^3 x 5 FP64 state array
 
 
-def source_hash() -> str:
+# Sources and compile flags that determine the fused 3D stage kernel.
+FUSED_FILES = ("wl2_device.hpp", "wl2_fused.hpp", "wl2_fused_launch.hpp", "wl2_fused3d.hip")
+
+
+def source_hash(files=FUSED_FILES, unit="wl2_fused3d.hip") -> str:
+    from .build import compile_flags
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
+    for name in files:
+        with open(os.path.join(PKG, "csrc", name), "rb") as fh:
+            h.update(name.encode())
             h.update(fh.read())
+    h.update(" ".join(compile_flags(unit)).encode())
     return h.hexdigest()[:16]
 
 

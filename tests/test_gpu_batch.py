@@ -1,0 +1,222 @@
+"""Batched and served forms on the GPU, through the C ABI.
+
+* A run's result does not depend on what else is in the batch: every run of
+  a ragged mix of 1D and 2D grids equals, bit for bit, the same run admitted
+  alone, and the same run on a single-grid context (weno_l2is_advance).
+* The batched results match the CPU oracle advanced to the same end time
+  (1e-10, the 100-step bar).
+* Admission is bounded by the HBM budget and the slot table; retirement frees
+  the memory for the next run.
+* A run that reaches a non-physical state is retired with its status, alone;
+  the other runs of the mix are unaffected.
+* The serving loop (Poisson arrivals, continuous admission) returns for every
+  request the result of running it alone.
+"""
+import numpy as np
+import pytest
+
+from paper_1908_02464_amd import workloads as w
+from gpu_util import params_pair, say, to_dev, to_host, z20
+
+pytestmark = pytest.mark.gpu
+G = 1.4
+MiB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def capi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1908_02464_amd import capi as c
+    c.lib()
+    return c
+
+
+def _mix():
+    """(name, U0, dx, t_end) of a ragged mix: 1D and 2D, sizes that leave
+    partial segments and partial wavefronts, 30-120 steps each."""
+    out = []
+    U, dx = w.sod(200)
+    out.append(("sod200", U, dx, 0.1))
+    left, right = w.random_two_state(np.random.default_rng(5))
+    U, dx = w.riemann_1d(333, left, right)
+    out.append(("two_state333", U, dx, 0.05))
+    U, dx = w.shu_osher(517)
+    out.append(("shu517", U, dx, 0.25))
+    U, dx, _ = w.four_quadrant_2d(48, 40, 21)
+    out.append(("quad48x40", U, dx, 0.08))
+    U, dx, _ = w.four_quadrant_2d(37, 29, 22)
+    out.append(("quad37x29", U, dx, 0.06))
+    U, dx = w.riemann_1d(9, *w.LAX)
+    out.append(("lax9", U, dx, 0.05))
+    return out
+
+
+def _shape(U):
+    nx = U.shape[-1]
+    ny = U.shape[-2] if U.ndim >= 3 else 1
+    return nx, ny, 1
+
+
+def _run_batch(capi, items, budget=256 * MiB, steps_per_poll=16):
+    eng = capi.Batch(budget, 64)
+    slots = {}
+    for name, U, dx, te in items:
+        nx, ny, nz = _shape(U)
+        s = eng.admit(U, nx, ny, nz, dx, te)
+        assert s is not None, name
+        slots[s] = name
+    res = {}
+    for _ in range(10000):
+        if len(res) == len(items):
+            break
+        eng.advance(steps_per_poll)
+        eng.stream.synchronize()
+        for s in eng.poll():
+            res[slots[s]] = eng.fetch(s)
+    eng.close()
+    assert len(res) == len(items)
+    return res
+
+
+def test_batch_mix_equals_alone_and_single_grid(capi):
+    import torch
+    items = _mix()
+    say("[batch] mix of", len(items), "runs")
+    mixed = _run_batch(capi, items)
+    for it in items:
+        name, U, dx, te = it
+        alone = _run_batch(capi, [it])[name]
+        Um, tm, sm = mixed[name]
+        Ua, ta, sa = alone
+        say(f"    {name}: t={tm} status={sm}")
+        assert sm == 0 and sa == 0 and tm == te and ta == te
+        assert np.array_equal(Um, Ua), name
+        nx, ny, nz = _shape(U)
+        ctx = capi.Context(nx, ny, nz, dx)
+        Ud = to_dev(U)
+        ctx.set_time(0.0)
+        while ctx.time()[0] < te:
+            ctx.advance(Ud, 64, te)
+        torch.cuda.synchronize()
+        Uc = to_host(Ud).reshape(Um.shape)
+        ctx.close()
+        d = float(np.abs(Uc - Um).max())
+        say(f"    {name}: |batch - single-grid| = {d:.3e}")
+        assert np.array_equal(Uc, Um), name
+
+
+def test_batch_vs_oracle(orc, capi):
+    items = _mix()
+    res = _run_batch(capi, items)
+    for name, U, dx, te in items:
+        nx, ny, nz = _shape(U)
+        po, _ = params_pair(orc, capi, (nx, ny, nz), dx)
+        Uo = U.copy()
+        t, n, st = orc.run(Uo, dx, G, po, te)
+        Ug, tg, sg = res[name]
+        err = z20(Ug.reshape(Uo.shape), Uo)
+        say(f"    {name}: steps={n} t={t} z20={err:.3e}")
+        assert st == 0 and sg == 0 and t == tg == te
+        assert err <= 1e-10, name
+
+
+def test_batch_budget_and_reuse(capi):
+    say("[batch] budget")
+    U1, dx1 = w.sod(1000)  # 3 arrays x 3 vars x 1000 x 8 B = 72000 B (+ alignment)
+    U2, dx2 = w.sod(1000)
+    eng = capi.Batch(100_000, 8)
+    s1 = eng.admit(U1, 1000, 1, 1, dx1, 0.01)
+    assert s1 is not None
+    used, act = eng.usage()
+    assert act == 1 and 72000 <= used <= 100_000
+    assert eng.admit(U2, 1000, 1, 1, dx2, 0.01) is None  # over budget
+    assert eng.usage() == (used, 1)
+    while True:
+        eng.advance(8)
+        eng.stream.synchronize()
+        done = eng.poll()
+        if done:
+            break
+    assert done == [s1]
+    U, t, st = eng.fetch(s1)
+    assert st == 0 and t == 0.01
+    assert eng.usage() == (0, 0)
+    s2 = eng.admit(U2, 1000, 1, 1, dx2, 0.01)
+    assert s2 is not None
+    with pytest.raises(capi.WenoL2ISError):
+        eng.fetch(7)  # never admitted
+    eng.close()
+    # slot table bound
+    eng = capi.Batch(64 * MiB, 2)
+    Us, dxs = w.sod(64)
+    assert eng.admit(Us, 64, 1, 1, dxs, 0.1) is not None
+    assert eng.admit(Us, 64, 1, 1, dxs, 0.1) is not None
+    assert eng.admit(Us, 64, 1, 1, dxs, 0.1) is None
+    eng.close()
+
+
+def test_batch_rejects_unsupported(capi):
+    eng = capi.Batch(64 * MiB, 4)
+    U3, dx3 = w.turbulence_3d(8, 0)
+    with pytest.raises(capi.WenoL2ISError):
+        eng.admit(U3, 8, 8, 8, dx3, 0.1)  # 3D runs use the single-grid path
+    Us, dxs = w.sod(64)
+    p = capi.params_default(64, 1, 1, dxs, split=capi.SPLIT_LF)
+    with pytest.raises(capi.WenoL2ISError):
+        eng.admit(Us, 64, 1, 1, dxs, 0.1, params=p)
+    with pytest.raises(capi.WenoL2ISError):
+        eng.admit(Us, 64, 1, 1, dxs, -1.0)
+    eng.close()
+
+
+def test_batch_nonphysical_retired_alone(capi):
+    say("[batch] non-physical run in a mix")
+    items = _mix()[:3]
+    bad, dxb = w.sod(128)
+    bad = bad.copy()
+    bad[2, 0, 0, 40] = -1.0  # negative energy: non-physical
+    eng = capi.Batch(64 * MiB, 16)
+    sb = eng.admit(bad, 128, 1, 1, dxb, 0.1)
+    eng.advance(1)
+    eng.stream.synchronize()
+    done = eng.poll()
+    assert done == [sb]
+    _, _, st = eng.fetch(sb)
+    assert st & 1
+    eng.close()
+    # with the bad run present for the whole time, the others are unchanged
+    good = _run_batch(capi, items)
+    eng = capi.Batch(64 * MiB, 16)
+    slots = {eng.admit(bad, 128, 1, 1, dxb, 0.1): "bad"}
+    for name, U, dx, te in items:
+        nx, ny, nz = _shape(U)
+        slots[eng.admit(U, nx, ny, nz, dx, te)] = name
+    res = {}
+    while len(res) < len(slots):
+        eng.advance(16)
+        eng.stream.synchronize()
+        for s in eng.poll():
+            res[slots[s]] = eng.fetch(s)
+    eng.close()
+    assert res["bad"][2] & 1
+    for name, *_ in items:
+        assert np.array_equal(res[name][0], good[name][0]), name
+
+
+def test_serving_equals_alone(capi):
+    from paper_1908_02464_amd import serve
+    reqs = w.request_stream(n_req=24, rate=500.0, seed=3, n1d=(40, 600), n2d=(12, 48),
+                            steps=(10, 80))
+    say("[serve] 24 requests, continuous admission under a small budget")
+    # a budget that holds only a few runs at once, so admission waits
+    out_b, span_b = serve.run_batched(reqs, budget_bytes=2 * MiB, max_slots=64, continuous=True,
+                                      steps_per_poll=4)
+    out_p, span_p = serve.run_plain(reqs, honour_arrivals=False)
+    s = serve.summarize(reqs, out_b, span_b)
+    say("    batched", s)
+    for r in reqs:
+        a, b = out_b[r.rid], out_p[r.rid]
+        assert a["status"] == 0 and b["status"] == 0, r.rid
+        assert a["t"] == b["t"] == r.t_end, r.rid
+        assert np.array_equal(a["U"], b["U"].reshape(a["U"].shape)), r.rid
