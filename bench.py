@@ -5,7 +5,9 @@ One "step" is one SSP-RK3 step (three right-hand-side stages plus the device
 CFL reduction) of the whole hot path on the 256^3 grid, inputs resident in
 HBM.  Prints one JSON line with the throughput in Mcell-updates/s per RK
 stage, the roofline of the dominant kernel (HIP events on the library's
-stream), and the CPU oracle timed on a bounded sample of the same workload.
+stream), the batched-serving leg (p50/p99 time-to-solution and throughput of
+a Poisson stream of 1D/2D runs, beside plain per-grid launches) and the CPU
+oracle timed on a bounded sample of the same 3D workload.
 """
 from __future__ import annotations
 
@@ -82,6 +84,11 @@ def main():
     ap.add_argument("--wpe", type=int, default=0, help="fused kernel waves per SIMD (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the batched-serving leg (Poisson stream of 1D/2D Riemann runs)")
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--plain-sample", type=int, default=96,
+                    help="requests in the plain per-grid baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of a state array (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -171,6 +178,29 @@ def main():
         torch.cuda.synchronize()
         del cp
 
+    ctx.close()
+    del Ud
+    torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serve:
+        # batched serving: 1024 independent 1D/2D Riemann runs arriving as a
+        # Poisson stream (200/s), admitted by HBM footprint into one batched
+        # launch sequence (continuous), the same stream as a closed batch,
+        # and the plain per-grid launches on a random sample of it
+        from paper_1908_02464_amd import serve
+        log(f"[bench] serving leg: {args.serve_requests} requests")
+        serving = serve.serve_stream(n_req=args.serve_requests, modes=("continuous", "closed", "plain"),
+                                     plain_sample=args.plain_sample, log=log)
+        for k in ("metric", "unit", "data", "dtype"):
+            serving.pop(k, None)
+        cont, plain = serving["continuous"], serving.get("plain_sample") or serving.get("plain")
+        serving["speedup_continuous_vs_plain"] = round(
+            cont["throughput_Mcell_stage_per_s"] / plain["throughput_Mcell_stage_per_s"], 2)
+        for m in ("continuous", "closed", "plain", "plain_sample"):
+            if m in serving and not serving[m].get("failed"):
+                serving[m].pop("failed_runs", None)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -217,9 +247,9 @@ def main():
             "frac_of_hbm_peak": round(path_gbs / HBM_PEAK_GBS, 4),
         },
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

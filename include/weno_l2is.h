@@ -111,6 +111,8 @@ int weno_l2is_step(weno_l2is_ctx *ctx, double *U, double dt);
 
 /* Advance U by n_steps CFL steps (dt from the device each step), stopping
  * exactly at t_end (> 0; the last step is clipped, later steps are no-ops).
+ * Steps after a non-physical state was seen (status bit set) are no-ops too:
+ * U keeps the last state the CFL reduction flagged.
  * The simulated time is kept on the device and read by weno_l2is_time. */
 int weno_l2is_advance(weno_l2is_ctx *ctx, double *U, int n_steps,
                       double t_end);
@@ -123,8 +125,11 @@ int weno_l2is_set_time(weno_l2is_ctx *ctx, double t);
  * non-physical cell was found (only known when dt_host != NULL). */
 int weno_l2is_cfl_dt(weno_l2is_ctx *ctx, const double *U, double *dt_host);
 
-/* Synchronize and read the dt used by the latest step and the device clock. */
-int weno_l2is_time(weno_l2is_ctx *ctx, double *t_host, double *last_dt_host);
+/* Synchronize and read the dt used by the latest step, the device clock and
+ * the number of clock steps taken since the context was created (steps of
+ * weno_l2is_advance that advanced the clock).  Any pointer may be NULL. */
+int weno_l2is_time(weno_l2is_ctx *ctx, double *t_host, double *last_dt_host,
+                   unsigned *steps);
 
 /* Per-face switch flags (1 = linear flux) and detector values sigma^s of
  * Eq.(30) along direction dir, computed by the same device code as the
@@ -205,10 +210,19 @@ int weno_l2is_batch_poll(weno_l2is_batch *b, int *done_slots, int cap,
                          int *n_done);
 
 /* Synchronize, copy the run's state to U_out (host if out_on_host, else
- * device), report its time and status bits, and free the slot and its
- * memory.  Returns WL2_E_SLOT for a slot not in use. */
+ * device), report its time, status bits and number of steps taken (t_out,
+ * status, steps may be NULL), and free the slot and its memory.  Returns WL2_E_SLOT for a slot not in use. */
 int weno_l2is_batch_fetch(weno_l2is_batch *b, int slot, double *U_out,
-                          int out_on_host, double *t_out, unsigned *status);
+                          int out_on_host, double *t_out, unsigned *status,
+                          unsigned *steps);
+
+/* Launch shape of the batched sweeps: `seg` cells per thread along a sweep
+ * (4, 8 or 16; the pencil length) and `blocks` workgroups in the persistent
+ * grid (64..65536); 0 keeps the current value.  Results do not depend on
+ * either (every face is computed by the same arithmetic), only the speed
+ * does; the captured graph is rebuilt on the next advance.  Returns
+ * WL2_E_PARAM for values outside these sets. */
+int weno_l2is_batch_tune(weno_l2is_batch *b, int seg, int blocks);
 
 /* Bytes of the budget in use and number of admitted runs. */
 int weno_l2is_batch_usage(weno_l2is_batch *b, size_t *used_bytes,

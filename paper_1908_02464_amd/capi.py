@@ -63,7 +63,7 @@ def lib():
         "weno_l2is_advance": (ip, [vp, vp, ip, dp]),
         "weno_l2is_set_time": (ip, [vp, dp]),
         "weno_l2is_cfl_dt": (ip, [vp, vp, C.POINTER(dp)]),
-        "weno_l2is_time": (ip, [vp, C.POINTER(dp), C.POINTER(dp)]),
+        "weno_l2is_time": (ip, [vp, C.POINTER(dp), C.POINTER(dp), C.POINTER(C.c_uint)]),
         "weno_l2is_face_debug": (ip, [vp, vp, ip, vp, vp]),
         "weno_l2is_status": (ip, [vp, C.POINTER(C.c_uint), ip]),
         "weno_l2is_tune": (ip, [vp, ip, ip, ip]),
@@ -76,8 +76,10 @@ def lib():
                                        C.POINTER(ip), C.POINTER(C.c_size_t)]),
         "weno_l2is_batch_advance": (ip, [vp, ip]),
         "weno_l2is_batch_poll": (ip, [vp, C.POINTER(ip), ip, C.POINTER(ip)]),
-        "weno_l2is_batch_fetch": (ip, [vp, ip, vp, ip, C.POINTER(dp), C.POINTER(C.c_uint)]),
+        "weno_l2is_batch_fetch": (ip, [vp, ip, vp, ip, C.POINTER(dp), C.POINTER(C.c_uint),
+                                       C.POINTER(C.c_uint)]),
         "weno_l2is_batch_usage": (ip, [vp, C.POINTER(C.c_size_t), C.POINTER(ip)]),
+        "weno_l2is_batch_tune": (ip, [vp, ip, ip]),
         "weno_l2is_batch_destroy": (None, [vp]),
         "weno_l2is_strerror": (C.c_char_p, [ip]),
     }
@@ -170,9 +172,14 @@ class Context:
         return dt.value, st
 
     def time(self):
-        t, dt = C.c_double(0.0), C.c_double(0.0)
-        _chk(lib().weno_l2is_time(self.h, C.byref(t), C.byref(dt)), "time")
-        return t.value, dt.value
+        """(device clock, dt of the latest step)."""
+        return self.clock()[:2]
+
+    def clock(self):
+        """(device clock, dt of the latest step, clock steps taken)."""
+        t, dt, n = C.c_double(0.0), C.c_double(0.0), C.c_uint(0)
+        _chk(lib().weno_l2is_time(self.h, C.byref(t), C.byref(dt), C.byref(n)), "time")
+        return t.value, dt.value, n.value
 
     def face_debug(self, U, d: int, flags, sigma):
         nf = self.ncell // self.shape[d] * (self.shape[d] + 1)
@@ -258,19 +265,24 @@ class Batch:
         _chk(lib().weno_l2is_batch_poll(self.h, arr, cap, C.byref(n)), "batch_poll")
         return [arr[i] for i in range(n.value)]
 
-    def fetch(self, slot: int):
+    def fetch(self, slot: int, with_steps: bool = False):
         """Copy the run's state to a host array, free the slot.
-        Returns (U, t, status)."""
+        Returns (U, t, status), or (U, t, status, steps) with with_steps."""
         import numpy as np
         if slot not in self.meta:
             raise WenoL2ISError(f"weno_l2is_batch_fetch: slot {slot} holds no run")
         nx, ny, nz = self.meta.pop(slot)
         dim, nvar, ncell = grid_dims(nx, ny, nz)
         U = np.empty((nvar, nz, ny, nx))
-        t, st = C.c_double(0.0), C.c_uint(0)
+        t, st, n = C.c_double(0.0), C.c_uint(0), C.c_uint(0)
         _chk(lib().weno_l2is_batch_fetch(self.h, int(slot), C.c_void_p(U.ctypes.data), 1,
-                                         C.byref(t), C.byref(st)), "batch_fetch")
-        return U, t.value, st.value
+                                         C.byref(t), C.byref(st), C.byref(n)), "batch_fetch")
+        return (U, t.value, st.value, n.value) if with_steps else (U, t.value, st.value)
+
+    def tune(self, seg: int = 0, blocks: int = 0):
+        """Pencil length (cells per thread) and persistent grid size of the
+        batched sweeps; 0 keeps the current value."""
+        _chk(lib().weno_l2is_batch_tune(self.h, int(seg), int(blocks)), "batch_tune")
 
     def usage(self):
         used, act = C.c_size_t(0), C.c_int(0)

@@ -70,17 +70,21 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
 }
 
 // dt = cfl dx / smax (or a fixed dt), clipped to the device clock when
-// use_clock; resets the running maximum for the next reduction.
+// use_clock (dt = 0, a no-op step, once the clock has reached t_end or a
+// non-physical state was seen); resets the running maximum for the next
+// reduction.
 [[maybe_unused]] static __global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / __longlong_as_double((long long)ctl->smax_bits);
   if (use_clock) {
+    // the clock stops at t_end and at the first non-physical state
     const double t = ctl->t, te = ctl->t_end;
-    if (!(t < te)) {
+    if (!(t < te) || ctl->status != 0u) {
       dt = 0.0;
     } else {
       if (t + dt > te) dt = te - t;
       ctl->t = t + dt;
+      ctl->steps += 1u;
     }
   }
   ctl->dt = dt;

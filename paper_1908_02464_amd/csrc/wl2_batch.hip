@@ -20,7 +20,7 @@ using namespace wl2;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int SWEEP_BLOCKS = 2048;  // persistent grid of the sweep kernels
+constexpr int SWEEP_BLOCKS_DEFAULT = 2048;  // persistent grid of the sweep kernels
 constexpr int RED_BLOCKS = 1024;
 
 struct SlotInfo {
@@ -71,6 +71,8 @@ struct weno_l2is_batch {
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  int seg = BATCH_SEG_DEFAULT;
+  int sweep_blocks = SWEEP_BLOCKS_DEFAULT;
 };
 
 namespace {
@@ -162,6 +164,22 @@ hipError_t upload_tables(weno_l2is_batch* b) {
   return hipSuccess;
 }
 
+void set_segments(const weno_l2is_batch* b, BGrid& G) {
+  const int nx = G.g.n[0], ny = G.g.n[1];
+  G.nseg[0] = (nx + b->seg - 1) / b->seg;
+  G.nseg[1] = (ny + b->seg - 1) / b->seg;
+  G.nthr[0] = (long long)G.nseg[0] * ny;
+  G.nthr[1] = G.dim == 2 ? (long long)G.nseg[1] * nx : 0;
+}
+
+template <int SEG>
+void enqueue_sweeps(weno_l2is_batch* b, int stage) {
+  hipLaunchKernelGGL((batch_sweep_kernel<0, SEG>), dim3(b->sweep_blocks), dim3(SWEEP_BLOCK), 0,
+                     b->stream, b->d_grids, b->d_tab + 0, stage);
+  hipLaunchKernelGGL((batch_sweep_kernel<1, SEG>), dim3(b->sweep_blocks), dim3(SWEEP_BLOCK), 0,
+                     b->stream, b->d_grids, b->d_tab + 1, stage);
+}
+
 // The launch sequence of one batched SSP-RK3 step.
 hipError_t enqueue_step(weno_l2is_batch* b) {
   hipStream_t st = b->stream;
@@ -171,10 +189,11 @@ hipError_t enqueue_step(weno_l2is_batch* b) {
   hipLaunchKernelGGL(batch_finalize_kernel, dim3(16), dim3(256), 0, st, b->d_grids, b->d_slotlist,
                      b->d_counts + 1);
   for (int stage = 0; stage < 3; ++stage) {
-    hipLaunchKernelGGL(batch_sweep_kernel<0>, dim3(SWEEP_BLOCKS), dim3(SWEEP_BLOCK), 0, st,
-                       b->d_grids, b->d_tab + 0, stage);
-    hipLaunchKernelGGL(batch_sweep_kernel<1>, dim3(SWEEP_BLOCKS), dim3(SWEEP_BLOCK), 0, st,
-                       b->d_grids, b->d_tab + 1, stage);
+    switch (b->seg) {
+      case 4: enqueue_sweeps<4>(b, stage); break;
+      case 16: enqueue_sweeps<16>(b, stage); break;
+      default: enqueue_sweeps<8>(b, stage); break;
+    }
   }
   return hipGetLastError();
 }
@@ -298,10 +317,7 @@ int weno_l2is_batch_admit(weno_l2is_batch* b, int nx, int ny, int nz, double dx,
   G.cfl_dx = p->cfl * dx;
   G.dim = si.dim;
   G.nv = si.nvar;
-  G.nseg[0] = (nx + BATCH_SEG - 1) / BATCH_SEG;
-  G.nseg[1] = (ny + BATCH_SEG - 1) / BATCH_SEG;
-  G.nthr[0] = (long long)G.nseg[0] * ny;
-  G.nthr[1] = si.dim == 2 ? (long long)G.nseg[1] * nx : 0;
+  set_segments(b, G);
   G.active = 1;
   StepCtl& C = b->h_ctl[s];
   std::memset(&C, 0, sizeof(C));
@@ -376,7 +392,7 @@ int weno_l2is_batch_poll(weno_l2is_batch* b, int* done_slots, int cap, int* n_do
 }
 
 int weno_l2is_batch_fetch(weno_l2is_batch* b, int slot, double* U_out, int out_on_host,
-                          double* t_out, unsigned* status) {
+                          double* t_out, unsigned* status, unsigned* steps) {
   if (!b || !U_out) return WL2_E_NULL;
   if (slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return WL2_E_SLOT;
   SlotInfo& si = b->slots[slot];
@@ -392,12 +408,40 @@ int weno_l2is_batch_fetch(weno_l2is_batch* b, int slot, double* U_out, int out_o
   b->upload_pending = false;
   if (t_out) *t_out = C.t;
   if (status) *status = C.status;
+  if (steps) *steps = C.steps;
   pool_free(b, si.off, si.bytes);
   si.used = false;
   b->h_grids[slot].active = 0;
   b->active--;
   b->dirty = true;
   b->state_pending = false;  // snapshots before this retirement are stale
+  return WL2_OK;
+}
+
+int weno_l2is_batch_tune(weno_l2is_batch* b, int seg, int blocks) {
+  if (!b) return WL2_E_NULL;
+  if (seg != 0 && seg != 4 && seg != 8 && seg != 16) return WL2_E_PARAM;
+  if (blocks != 0 && (blocks < 64 || blocks > 65536)) return WL2_E_PARAM;
+  const int new_seg = seg ? seg : b->seg;
+  const int new_blocks = blocks ? blocks : b->sweep_blocks;
+  if (new_seg == b->seg && new_blocks == b->sweep_blocks) return WL2_OK;
+  hipError_t e = wait_upload(b);
+  if (e != hipSuccess) return WL2_E_HIP;
+  b->seg = new_seg;
+  b->sweep_blocks = new_blocks;
+  // segment counts of the admitted runs follow the pencil length
+  for (int s = 0; s < b->max_slots; ++s)
+    if (b->slots[s].used) set_segments(b, b->h_grids[s]);
+  if ((e = hipMemcpyAsync(b->d_grids, b->h_grids, sizeof(BGrid) * b->max_slots,
+                          hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (e = hipEventRecord(b->ev_upload, b->stream)) != hipSuccess)
+    return WL2_E_HIP;
+  b->upload_pending = true;
+  b->dirty = true;  // work tables depend on the segment counts
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
   return WL2_OK;
 }
 

@@ -26,7 +26,7 @@ struct BGrid {
   int pad;
 };
 
-constexpr int BATCH_SEG = 8;
+constexpr int BATCH_SEG_DEFAULT = 8;
 constexpr int BATCH_MAX_SLOTS = 4096;
 constexpr int BATCH_CHUNK = 4096;  // cells per reduction chunk
 
@@ -62,8 +62,9 @@ __device__ __forceinline__ int table_find(const BTable* t, long long i) {
 }
 
 // PH = 0: x sweeps of all grids (1D: with the RK combination; 2D: into acc);
-// PH = 1: y sweeps of the 2D grids (with the RK combination).
-template <int PH>
+// PH = 1: y sweeps of the 2D grids (with the RK combination).  SEG cells per
+// thread along the sweep (BGrid::nseg was computed for the same SEG).
+template <int PH, int SEG>
 __global__ __launch_bounds__(SWEEP_BLOCK) void batch_sweep_kernel(const BGrid* __restrict__ grids,
                                                                   const BTable* __restrict__ tab,
                                                                   int stage) {
@@ -82,15 +83,15 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void batch_sweep_kernel(const BGrid* _
     if (G.dim == 1) {
       if (PH == 0) {
         SweepArgs a{Uk, out, nullptr, G.U, G.ctl, ra, rb};
-        sweep_body<3, 0, BATCH_SEG, OUT_RK>(a, G.g, G.ph, G.nseg[0], gid);
+        sweep_body<3, 0, SEG, OUT_RK>(a, G.g, G.ph, G.nseg[0], gid);
       }
     } else {
       if (PH == 0) {
         SweepArgs a{Uk, G.acc, nullptr, nullptr, G.ctl, 0.0, 1.0};
-        sweep_body<4, 0, BATCH_SEG, OUT_WRITE>(a, G.g, G.ph, G.nseg[0], gid);
+        sweep_body<4, 0, SEG, OUT_WRITE>(a, G.g, G.ph, G.nseg[0], gid);
       } else {
         SweepArgs a{Uk, out, G.acc, G.U, G.ctl, ra, rb};
-        sweep_body<4, 1, BATCH_SEG, OUT_RK>(a, G.g, G.ph, G.nseg[1], gid);
+        sweep_body<4, 1, SEG, OUT_RK>(a, G.g, G.ph, G.nseg[1], gid);
       }
     }
   }
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_cfl_kernel(const BGrid* __res
     } else {
       if (t + dt > te) dt = te - t;
       ctl->t = t + dt;
+      ctl->steps += 1u;
     }
     ctl->dt = dt;
     ctl->smax_bits = 0ull;

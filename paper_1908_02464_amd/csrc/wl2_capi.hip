@@ -400,7 +400,7 @@ int weno_l2is_cfl_dt(weno_l2is_ctx* c, const double* U, double* dt_host) {
   return (h.status & 1u) ? WL2_S_NONPHYSICAL : WL2_OK;
 }
 
-int weno_l2is_time(weno_l2is_ctx* c, double* t_host, double* last_dt_host) {
+int weno_l2is_time(weno_l2is_ctx* c, double* t_host, double* last_dt_host, unsigned* steps) {
   if (!c) return WL2_E_NULL;
   StepCtl h;
   hipError_t e = hipMemcpyAsync(&h, c->ctl, sizeof(h), hipMemcpyDeviceToHost, c->stream);
@@ -408,6 +408,7 @@ int weno_l2is_time(weno_l2is_ctx* c, double* t_host, double* last_dt_host) {
   if (e != hipSuccess) return WL2_E_HIP;
   if (t_host) *t_host = h.t;
   if (last_dt_host) *last_dt_host = h.dt;
+  if (steps) *steps = h.steps;
   return WL2_OK;
 }
 

@@ -54,7 +54,7 @@ struct KPhys {
 struct StepCtl {
   unsigned long long smax_bits;  // running max of sum_d(|u_d|+c) as raw bits
   unsigned int status;           // sticky: bit 0 = non-physical state seen
-  unsigned int pad;
+  unsigned int steps;            // clock steps taken (steps that advanced t)
   double dt;                     // dt of the step in flight
   double t;                      // simulated time after the step in flight
   double t_end;                  // > 0: clip the clock to it

@@ -1,7 +1,6 @@
-// Launch interface of the fused 3D stage kernels, which live in a translation
-// unit of their own (wl2_fused3d.hip) so that they can be compiled with
-// cross-statement FMA contraction while the sweep kernels keep contraction
-// inside single expressions (see build.py).
+// Launch interface of the fused 3D stage kernels, which live in a
+// translation unit of their own (wl2_fused3d.hip): the heaviest compile of the
+// library, built in parallel with the others.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -23,9 +23,9 @@ import torch
 from . import capi
 
 
-def _cell_stages(req):
+def _cell_stages(req, steps):
     nx, ny, nz = req.shape
-    return nx * ny * nz * 3 * req.target_steps
+    return nx * ny * nz * 3 * steps
 
 
 def run_plain(requests, steps_per_sync: int = 64, honour_arrivals: bool = True):
@@ -44,22 +44,25 @@ def run_plain(requests, steps_per_sync: int = 64, honour_arrivals: bool = True):
         ctx.set_time(0.0)
         while True:
             ctx.advance(U, steps_per_sync, r.t_end)
-            t, _ = ctx.time()
+            t, _, nsteps = ctx.clock()
             if not t < r.t_end or ctx.status() != 0:
                 break
         res = U.cpu().numpy()
         done = time.perf_counter() - t0
-        out[r.rid] = {"U": res, "t": t, "status": ctx.status(), "arrival": r.arrival,
-                      "finish": done}
+        out[r.rid] = {"U": res, "t": t, "status": ctx.status(), "steps": nsteps,
+                      "arrival": r.arrival, "finish": done}
         ctx.close()
     return out, time.perf_counter() - t0
 
 
 def run_batched(requests, budget_bytes: int, max_slots: int = 1024, continuous: bool = True,
-                steps_per_poll: int = 4, keep_results: bool = True):
+                steps_per_poll: int = 4, keep_results: bool = True, shape=None):
     """Batched execution; continuous=True honours arrival times (serving),
-    False admits everything as soon as memory allows (closed batch)."""
+    False admits everything as soon as memory allows (closed batch).
+    shape = (seg, blocks) of the batched sweeps (e.g. from the autotuner)."""
     eng = capi.Batch(budget_bytes, max_slots)
+    if shape:
+        eng.tune(*shape)
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     slot_req = {}
     out = {}
@@ -81,9 +84,10 @@ def run_batched(requests, budget_bytes: int, max_slots: int = 1024, continuous: 
             eng.stream.synchronize()
             for slot in eng.poll():
                 r = slot_req.pop(slot)
-                U, t, st = eng.fetch(slot)
+                U, t, st, nsteps = eng.fetch(slot, with_steps=True)
                 # a closed batch has every request in hand at time 0
                 out[r.rid] = {"U": U if keep_results else None, "t": t, "status": st,
+                              "steps": nsteps,
                               "arrival": r.arrival if continuous else 0.0,
                               "finish": time.perf_counter() - t0}
         elif pending:
@@ -95,24 +99,25 @@ def run_batched(requests, budget_bytes: int, max_slots: int = 1024, continuous: 
 
 def summarize(requests, out, makespan):
     lat = np.array([out[r.rid]["finish"] - out[r.rid]["arrival"] for r in requests])
-    work = sum(_cell_stages(r) for r in requests)
+    work = sum(_cell_stages(r, out[r.rid]["steps"]) for r in requests)
     return {
         "requests": len(requests),
         "makespan_s": round(makespan, 4),
         "p50_s": round(float(np.percentile(lat, 50)), 5),
         "p99_s": round(float(np.percentile(lat, 99)), 5),
         "mean_s": round(float(lat.mean()), 5),
+        "steps": int(sum(out[r.rid]["steps"] for r in requests)),
         "throughput_Mcell_stage_per_s": round(work / makespan / 1e6, 2),
         "failed": int(sum(1 for r in requests if out[r.rid]["status"] != 0)),
+        "failed_runs": [{"rid": r.rid, "shape": list(r.shape), "steps": out[r.rid]["steps"],
+                         "t": out[r.rid]["t"], "t_end": r.t_end}
+                        for r in requests if out[r.rid]["status"] != 0],
     }
 
 
 def main(argv=None):
     """Run one request stream three ways and print one JSON line."""
     import argparse
-    import json
-
-    from . import workloads
 
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--n-req", type=int, default=1024)
@@ -123,35 +128,74 @@ def main(argv=None):
     ap.add_argument("--steps-max", type=int, default=2000)
     ap.add_argument("--steps-per-poll", type=int, default=4)
     ap.add_argument("--modes", default="continuous,closed,plain")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="run the plain baseline on this many random requests only")
     a = ap.parse_args(argv)
-    reqs = workloads.request_stream(n_req=a.n_req, rate=a.rate, seed=a.seed,
-                                    steps=(a.steps_min, a.steps_max))
-    budget = int(a.budget_gib * (1 << 30))
+    return serve_stream(a.n_req, a.rate, a.seed, a.budget_gib, (a.steps_min, a.steps_max),
+                        a.steps_per_poll, a.modes.split(","), not a.no_autotune, a.plain_sample)
+
+
+def serve_stream(n_req=1024, rate=200.0, seed=0, budget_gib=4.0, steps=(50, 2000),
+                 steps_per_poll=4, modes=("continuous", "closed", "plain"), autotune=True,
+                 plain_sample=0, log=print):
+    """Run one seeded request stream in each mode; returns a dict with the
+    per-mode summaries and whether all modes gave the same bits.
+    plain_sample > 0 runs the plain per-grid baseline on that many requests
+    drawn at random from the stream (back to back, arrival times ignored), a
+    bounded throughput sample instead of the whole stream."""
+    import json
+
+    from . import autotune as tuner
+    from . import workloads
+
+    reqs = workloads.request_stream(n_req=n_req, rate=rate, seed=seed, steps=steps)
+    budget = int(budget_gib * (1 << 30))
+    shape = None
+    if autotune:
+        seg, blocks, times = tuner.tune_batch(reqs, budget, steps=4, max_runs=256)
+        shape = (seg, blocks)
+        log(f"[serve] autotuned batched sweeps: seg={seg} blocks={blocks} "
+            f"({times[shape]:.3f} ms/step on {min(256, n_req)} runs)")
     out = {"metric": "served time-to-solution p50/p99 and Mcell-updates/s per RK stage",
            "unit": "s; Mcell-updates/s", "data": "synthetic", "dtype": "f64",
-           "config": {"workload": f"{a.n_req} Poisson Riemann runs at {a.rate}/s, 70% 1D "
+           "config": {"workload": f"{n_req} Poisson Riemann runs at {rate}/s, 70% 1D "
                                   f"N in [128,8192], 30% 2D side in [64,512], "
-                                  f"{a.steps_min}-{a.steps_max} steps",
-                      "budget_bytes": budget}}
+                                  f"{steps[0]}-{steps[1]} steps",
+                      "budget_bytes": budget, "seed": seed,
+                      "batched_shape": {"seg": shape[0], "blocks": shape[1]} if shape else None}}
     results = {}
-    for mode in a.modes.split(","):
+    for mode in modes:
         torch.cuda.synchronize()
-        if mode == "plain":
+        if mode == "plain" and 0 < plain_sample < len(reqs):
+            pick = np.random.default_rng(seed + 1).choice(len(reqs), plain_sample, replace=False)
+            sub = [reqs[i] for i in sorted(pick)]
+            res, span = run_plain(sub, honour_arrivals=False)
+            name = "plain_sample"
+            out[name] = summarize(sub, res, span)
+            out[name]["note"] = (f"{plain_sample} requests drawn at random from the stream, "
+                                 "run back to back (latencies not comparable)")
+        elif mode == "plain":
             res, span = run_plain(reqs)
+            name = mode
+            out[name] = summarize(reqs, res, span)
         else:
             res, span = run_batched(reqs, budget, continuous=(mode == "continuous"),
-                                    steps_per_poll=a.steps_per_poll)
-        out[mode] = summarize(reqs, res, span)
-        results[mode] = res
-        print(f"[serve] {mode}: {out[mode]}", flush=True)
-    modes = list(results)
+                                    steps_per_poll=steps_per_poll, shape=shape)
+            name = mode
+            out[name] = summarize(reqs, res, span)
+        results[name] = res
+        log(f"[serve] {name}: {out[name]}")
+    names = list(results)
     same = True
-    for m in modes[1:]:
+    for m in names[1:]:
         for r in reqs:
-            x, y = results[modes[0]][r.rid]["U"], results[m][r.rid]["U"]
-            same = same and np.array_equal(x, y.reshape(x.shape))
+            if r.rid not in results[m] or r.rid not in results[names[0]]:
+                continue
+            x, y = results[names[0]][r.rid]["U"], results[m][r.rid]["U"]
+            same = same and np.array_equal(x, y.reshape(x.shape), equal_nan=True)
     out["bitwise_equal_across_modes"] = same
-    print(json.dumps(out), flush=True)
+    log(json.dumps(out))
     return out
 
 

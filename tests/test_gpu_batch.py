@@ -58,8 +58,10 @@ def _shape(U):
     return nx, ny, 1
 
 
-def _run_batch(capi, items, budget=256 * MiB, steps_per_poll=16):
+def _run_batch(capi, items, budget=256 * MiB, steps_per_poll=16, shape=None):
     eng = capi.Batch(budget, 64)
+    if shape:
+        eng.tune(*shape)
     slots = {}
     for name, U, dx, te in items:
         nx, ny, nz = _shape(U)
@@ -219,4 +221,79 @@ def test_serving_equals_alone(capi):
         a, b = out_b[r.rid], out_p[r.rid]
         assert a["status"] == 0 and b["status"] == 0, r.rid
         assert a["t"] == b["t"] == r.t_end, r.rid
+        assert a["steps"] == b["steps"] > 0, r.rid
         assert np.array_equal(a["U"], b["U"].reshape(a["U"].shape)), r.rid
+
+
+def test_batch_results_independent_of_launch_shape(capi):
+    """Pencil length and persistent grid size change no bit of any run."""
+    items = _mix()
+    ref = _run_batch(capi, items)
+    for shape in [(4, 512), (16, 8192), (8, 64)]:
+        say(f"[batch] seg={shape[0]} blocks={shape[1]}")
+        got = _run_batch(capi, items, shape=shape)
+        for name, *_ in items:
+            assert np.array_equal(got[name][0], ref[name][0]), (name, shape)
+    eng = capi.Batch(MiB, 4)
+    for bad in [(3, 0), (32, 0), (0, 63), (0, 65537)]:
+        with pytest.raises(capi.WenoL2ISError):
+            eng.tune(*bad)
+    eng.close()
+
+
+def test_batch_tune_mid_run(capi):
+    """Changing the launch shape between advances of admitted runs."""
+    items = _mix()
+    ref = _run_batch(capi, items)
+    eng = capi.Batch(256 * MiB, 64)
+    slots = {}
+    for name, U, dx, te in items:
+        nx, ny, nz = _shape(U)
+        slots[eng.admit(U, nx, ny, nz, dx, te)] = name
+    res, k = {}, 0
+    shapes = [(4, 1024), (16, 2048), (8, 4096)]
+    while len(res) < len(items):
+        eng.tune(*shapes[k % 3])
+        k += 1
+        eng.advance(7)
+        eng.stream.synchronize()
+        for s in eng.poll():
+            res[slots[s]] = eng.fetch(s)
+    eng.close()
+    for name, *_ in items:
+        assert np.array_equal(res[name][0], ref[name][0]), name
+
+
+def test_autotuner_batch(capi):
+    from paper_1908_02464_amd import autotune
+    reqs = w.request_stream(n_req=16, rate=1000.0, seed=9, n1d=(64, 2000), n2d=(16, 128))
+    seg, blocks, times = autotune.tune_batch(reqs, 64 * MiB, steps=2, segs=(4, 8),
+                                             blocks=(512, 2048), verbose=True)
+    assert (seg, blocks) in times and len(times) == 4
+    assert all(t > 0 for t in times.values())
+
+
+def test_fused_zchunk_bitwise_and_autotuner(capi):
+    """z planes per workgroup and the occupancy target of the fused 3D kernel
+    change no result bit; the tuner returns one of the timed shapes."""
+    import torch
+    from paper_1908_02464_amd import autotune
+    U, dx = w.turbulence_3d(32, 4)
+    U = U.copy()
+    U[0, :, :, :16] *= 2.0
+    U[4, :, :, :16] *= 2.0
+    outs = []
+    for zc, wpe in ((0, 2), (8, 2), (16, 1), (32, 2), (5, 1)):
+        ctx = capi.Context(32, 32, 32, dx)
+        ctx.tune(capi.PATH_FUSED, zc, wpe)
+        Ud = to_dev(U)
+        for _ in range(3):
+            ctx.step(Ud)
+        torch.cuda.synchronize()
+        outs.append(to_host(Ud))
+        ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    zc, wpe, times = autotune.tune_fused(32, 32, 32, dx, to_dev(U), steps=2, zchunks=(0, 8, 32),
+                                         verbose=True)
+    assert (zc, wpe) in times and len(times) == 6
