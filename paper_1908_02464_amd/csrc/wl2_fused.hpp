@@ -383,17 +383,33 @@ __device__ __forceinline__ Col make_col(const KGrid& g, int x, int y) {
   return c;
 }
 
+// Cell z of a column, as stored (a reflective ghost is the mirror cell; its
+// normal momentum is negated by col_flip when the value is used, so that a
+// prefetch does not have to wait for the load).
 template <int NV>
-__device__ __forceinline__ void load_col(const double* __restrict__ U, const KGrid& g, const Col& c,
-                                         int z, double (&u)[NV]) {
+__device__ __forceinline__ void load_col_raw(const double* __restrict__ U, const KGrid& g,
+                                             const Col& c, int z, double (&u)[NV]) {
   bool fz = false;
   const int iz = (z >= 0 && z < g.n[2]) ? z : ghost_clamped(z, g.n[2], g.bc_lo[2], g.bc_hi[2], fz);
   const long long off = c.xy + (long long)iz * g.stride[2];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
+}
+
+template <int NV>
+__device__ __forceinline__ void col_flip(const KGrid& g, const Col& c, int z, double (&u)[NV]) {
+  bool fz = false;
+  if (z < 0 || z >= g.n[2]) (void)ghost_clamped(z, g.n[2], g.bc_lo[2], g.bc_hi[2], fz);
   if (c.fx) u[1] = -u[1];
   if (c.fy) u[2] = -u[2];
   if (fz) u[3] = -u[3];
+}
+
+template <int NV>
+__device__ __forceinline__ void load_col(const double* __restrict__ U, const KGrid& g, const Col& c,
+                                         int z, double (&u)[NV]) {
+  load_col_raw<NV>(U, g, c, z, u);
+  col_flip<NV>(g, c, z, u);
 }
 
 // z stencil of a column owner: cells j-2, j-1 from the per-column LDS ring,
@@ -479,6 +495,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   double Fzp[NV];
   bool zprev = false;  // face z - 1/2 needs the nonlinear flux
   double upre[NV], hpre[NV];
+  double unp[NV] = {};  // U^n of cell z (RK stages 2, 3), loaded a phase ahead
   if (owner) {
     double u[NV];
     LRec<NV> c0, c1;
@@ -510,9 +527,9 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     // face z0 - 1/2 (cells z0-3 .. z0+2): window c0, c1, r0, r1, r2, r3
     const WinSrc<NV> src{c0, c1, r0, r1, r2, r3};
     zprev = face_linear_l<NV, 2, SPLIT, HYB>(src, ph, ph.eps_thr[2], lfz, Fzp) != 0u;
-    load_col<NV>(a.Uk, g, ocol, z0 + 3, upre);
+    load_col_raw<NV>(a.Uk, g, ocol, z0 + 3, upre);
   }
-  if (t < NHALO) load_col<NV>(a.Uk, g, hcol, z0, hpre);
+  if (t < NHALO) load_col_raw<NV>(a.Uk, g, hcol, z0, hpre);
 
   for (int z = z0; z < z1; ++z) {
     if (owner) {
@@ -527,15 +544,33 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       r0 = r1;
       r1 = r2;
       r2 = r3;
+      col_flip<NV>(g, ocol, z + 3, upre);
       make_lrec<NV>(upre, ph, r3);
-      if (z + 1 < z1) load_col<NV>(a.Uk, g, ocol, z + 4, upre);
       lds_put<NV>(srec, lds_own, r0);  // cell z
+      // The prefetch of cell z+4 lands in the registers just consumed.  The
+      // empty asm (a compiler memory barrier that takes the new record as
+      // input) keeps the loads below the last use of the old values: loads
+      // hoisted above it need other registers and a copy, and the copy waits
+      // for the load.  The load is unconditional (past the chunk the index is
+      // ghost-clamped and stays in bounds) for the same reason.
+      asm volatile("" ::"v"(r3.U[0]), "v"(r3.U[1]), "v"(r3.U[2]), "v"(r3.U[3]), "v"(r3.U[4]),
+                   "v"(r3.p), "v"(r3.c), "v"(r3.iw)
+                   : "memory");
+      load_col_raw<NV>(a.Uk, g, ocol, z + 4, upre);
+      if (OUT == OUT_RK && a.rk_a != 0.0) {
+        // clamped column (equal to the cell's own index for valid owners)
+        const long long offn = ocol.xy + (long long)z * g.stride[2];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) unp[v] = a.Un[v * g.ncell + offn];
+      }
     }
     if (t < NHALO) {
       LRec<NV> hrec;
+      col_flip<NV>(g, hcol, z, hpre);
       make_lrec<NV>(hpre, ph, hrec);
       lds_put<NV>(srec, lds_halo, hrec);
-      if (z + 1 < z1) load_col<NV>(a.Uk, g, hcol, z + 1, hpre);
+      asm volatile("" ::: "memory");  // as above: the prefetch after the last use
+      load_col_raw<NV>(a.Uk, g, hcol, z + 1, hpre);
     }
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
@@ -597,7 +632,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
                              (Fzp[v] - Fz[v])) * ph.inv_dx;
           if (OUT == OUT_RK) {
             double r = a.rk_b * (r0.U[v] + dt * dU);
-            if (a.rk_a != 0.0) r += a.rk_a * a.Un[v * g.ncell + off];
+            if (a.rk_a != 0.0) r += a.rk_a * unp[v];
             a.out[v * g.ncell + off] = r;
           } else {
             a.out[v * g.ncell + off] = dU;
