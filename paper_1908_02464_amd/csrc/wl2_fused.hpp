@@ -30,12 +30,13 @@ constexpr int NXF = (FT_X + 1) * FT_Y;           // 255 x faces per plane
 constexpr int NYF = FT_X * (FT_Y + 1);           // 256 y faces per plane
 constexpr int NHALO = 6 * FT_Y + 6 * FT_X;       // 186 halo cells per plane
 
-// 1/x and 1/sqrt(x) from the hardware seeds refined by Newton steps (not
-// correctly rounded; a few ulp, see DESIGN notes on precision).
+// 1/x and 1/sqrt(x) from the hardware seeds refined by two Newton steps (the
+// seed error squares each step; the result is within a few ulp, not
+// correctly rounded).
 __device__ __forceinline__ double fast_rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 2; ++i) {
     const double e = fma(-x, r, 1.0);
     r = fma(r, e, r);
   }
@@ -46,7 +47,7 @@ __device__ __forceinline__ double fast_rsqrt(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double h = 0.5 * x;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 2; ++i) {
     const double e = fma(-h * y, y, 0.5);
     y = fma(y, e, y);
   }
