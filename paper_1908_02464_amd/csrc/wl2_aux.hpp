@@ -7,12 +7,6 @@ namespace wl2 {
 
 constexpr int RED_BLOCK = 256;
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 // Block maximum of non-negative values; NaN propagates (any NaN wins).
 __device__ __forceinline__ double block_max(double v, double* sh) {
   const bool nan = (v != v);
@@ -28,9 +22,9 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
-// max over cells of sum_d (|u_d| + c), same operation order as the
-// definition dt = cfl dx / max_cells sum_d (|u_d| + c); contraction off so
-// the result is reproducible bit for bit.  Non-physical cells set status.
+// max over cells of sum_d (|u_d| + c) (cfl_speed: the operation order of the
+// definition dt = cfl dx / max_cells sum_d (|u_d| + c), reproducible bit for
+// bit).  Non-physical cells set status.
 template <int NV>
 __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __restrict__ U,
                                                                long long ncell, double gamma,
@@ -42,24 +36,10 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
   bool bad = false;
   for (long long c = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; c < ncell;
        c += (long long)gridDim.x * RED_BLOCK) {
-    const double rho = U[c], E = U[(NV - 1) * ncell + c];
-    double vel[DIM], q = 0.0;
-    bool fin = isfinite(rho) && isfinite(E);
+    double m[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const double m = U[(1 + k) * ncell + c];
-      fin = fin && isfinite(m);
-      vel[k] = m / rho;
-      q += vel[k] * vel[k];
-    }
-    q *= 0.5;
-    const double p = (gamma - 1.0) * (E - rho * q);
-    const double cs = sqrt(gamma * p / rho);
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) s += fabs(vel[k]) + cs;
-    if (!fin || !(rho > 0.0) || !(p > 0.0)) bad = true;
-    if (s != s || s > smax) smax = s;
+    for (int k = 0; k < DIM; ++k) m[k] = U[(1 + k) * ncell + c];
+    smax = nan_max(smax, cfl_speed<DIM>(U[c], m, U[(NV - 1) * ncell + c], gamma, bad));
   }
   const double bm = block_max(smax, sh);
   if (threadIdx.x == 0) {
@@ -91,9 +71,13 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
   ctl->smax_bits = 0ull;
 }
 
-// Program the device clock target (enqueued, no host synchronisation).
+// Program the device clock target (enqueued, no host synchronisation) and
+// clear the running CFL maximum.
 [[maybe_unused]] static __global__ void set_t_end_kernel(StepCtl* ctl, double t_end) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t_end = t_end;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->t_end = t_end;
+    ctl->smax_bits = 0ull;  // a maximum left by an earlier call is stale
+  }
 }
 
 // Global LF speeds along every active direction: max over cells of

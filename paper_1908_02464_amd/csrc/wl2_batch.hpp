@@ -115,23 +115,13 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_cfl_kernel(const BGrid* __res
     bool bad = false;
     for (int q = threadIdx.x; q < cnt; q += RED_BLOCK) {
       const long long cc = c0 + q;
-      const int DIM = G.dim;
-      const double rho = U[cc], E = U[(DIM + 1) * nc + cc];
-      double vel[3] = {0.0, 0.0, 0.0}, qq = 0.0;
-      bool fin = isfinite(rho) && isfinite(E);
-      for (int k = 0; k < DIM; ++k) {
-        const double m = U[(1 + k) * nc + cc];
-        fin = fin && isfinite(m);
-        vel[k] = m / rho;
-        qq += vel[k] * vel[k];
+      if (G.dim == 1) {
+        const double m[1] = {U[nc + cc]};
+        smax = nan_max(smax, cfl_speed<1>(U[cc], m, U[2 * nc + cc], gamma, bad));
+      } else {
+        const double m[2] = {U[nc + cc], U[2 * nc + cc]};
+        smax = nan_max(smax, cfl_speed<2>(U[cc], m, U[3 * nc + cc], gamma, bad));
       }
-      qq *= 0.5;
-      const double p = (gamma - 1.0) * (E - rho * qq);
-      const double cs = sqrt(gamma * p / rho);
-      double s = 0.0;
-      for (int k = 0; k < DIM; ++k) s += fabs(vel[k]) + cs;
-      if (!fin || !(rho > 0.0) || !(p > 0.0)) bad = true;
-      if (s != s || s > smax) smax = s;
     }
     const double bm = block_max(smax, sh);
     if (threadIdx.x == 0 && (bm > 0.0 || bm != bm))

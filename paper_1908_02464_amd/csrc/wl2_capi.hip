@@ -135,8 +135,12 @@ unsigned red_blocks(long long ncell) {
   return (unsigned)b;
 }
 
-hipError_t launch_cfl(const weno_l2is_ctx* c, const double* U, double dt_fixed, int use_clock) {
-  if (dt_fixed <= 0.0) {
+// dt of the next step: the CFL reduction of U (skipped when the previous
+// stage kernel already folded the maximum of U into the control word), then
+// the finalisation.
+hipError_t launch_cfl(const weno_l2is_ctx* c, const double* U, double dt_fixed, int use_clock,
+                      bool reduced = false) {
+  if (dt_fixed <= 0.0 && !reduced) {
     const unsigned b = red_blocks(c->ncell);
     TimedLaunch tl(c, "cfl_reduce");
     switch (c->nvar) {
@@ -178,12 +182,13 @@ int fused_zchunk(const weno_l2is_ctx* c) {
 }
 
 hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
-                        const double* Un, double ra, double rb) {
+                        const double* Un, double ra, double rb, bool fold_cfl = false) {
   FusedLaunch L;
   L.Uk = Uk;
   L.out = out;
   L.Un = Un;
   L.ctl = c->ctl;
+  L.cfl = fold_cfl ? c->ctl : nullptr;
   L.list = c->list;
   L.rk_a = ra;
   L.rk_b = rb;
@@ -220,12 +225,13 @@ hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
   return hipSuccess;
 }
 
-// One RK stage: out = a Un + b (Uk + dt L(Uk)).
+// One RK stage: out = a Un + b (Uk + dt L(Uk)).  fold_cfl (fused path): the
+// stage kernels also fold the CFL maximum of `out` into the control word.
 hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, double* out,
-                 double ra, double rb) {
+                 double ra, double rb, bool fold_cfl = false) {
   hipError_t e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
-  if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb);
+  if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
   for (int d = 0; d < c->dim - 1; ++d) {
     SweepArgs a{Uk, c->acc, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -234,11 +240,11 @@ hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, dou
   return launch_sweep(c, c->dim - 1, OUT_RK, a);
 }
 
-hipError_t rk3(const weno_l2is_ctx* c, double* U) {
+hipError_t rk3(const weno_l2is_ctx* c, double* U, bool fold_cfl = false) {
   hipError_t e;
   if ((e = stage(c, U, nullptr, c->U1, 0.0, 1.0)) != hipSuccess) return e;
   if ((e = stage(c, c->U1, U, c->U2, 0.75, 0.25)) != hipSuccess) return e;
-  return stage(c, c->U2, U, U, 1.0 / 3.0, 2.0 / 3.0);
+  return stage(c, c->U2, U, U, 1.0 / 3.0, 2.0 / 3.0, fold_cfl);
 }
 
 std::mutex g_cache_mu;
@@ -367,9 +373,14 @@ int weno_l2is_advance(weno_l2is_ctx* c, double* U, int n_steps, double t_end) {
   if (n_steps < 0 || !(t_end > 0.0) || !std::isfinite(t_end)) return WL2_E_PARAM;
   hipLaunchKernelGGL(set_t_end_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t_end);
   hipError_t e = hipGetLastError();
+  // fused path: the last stage of a step also reduces the CFL speed of the
+  // new state (its cells are in registers there), so every step after the
+  // first of this call skips the separate reduction.  Within one call U is
+  // only touched here, so the folded maximum is that of U.
+  const bool fold = use_fused(c);
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
-    e = launch_cfl(c, U, 0.0, 1);
-    if (e == hipSuccess) e = rk3(c, U);
+    e = launch_cfl(c, U, 0.0, 1, fold && s > 0);
+    if (e == hipSuccess) e = rk3(c, U, fold && s + 1 < n_steps);
   }
   return hip_err(e);
 }

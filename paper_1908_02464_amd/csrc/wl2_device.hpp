@@ -63,6 +63,55 @@ struct StepCtl {
   unsigned int pad2;
 };
 
+// ---------------------------------------------------------------- CFL
+// Signal speed sum_d (|u_d| + c) of one cell, in the operation order of the
+// time-step definition (correctly rounded division and square root, no
+// contraction), so every kernel that reduces it gets the same bits; sets
+// bad for a non-finite or non-physical (rho <= 0 or p <= 0) state.
+template <int DIM>
+__device__ __forceinline__ double cfl_speed(double rho, const double (&m)[DIM], double E,
+                                            double gamma, bool& bad) {
+#pragma clang fp contract(off)
+  double vel[DIM], q = 0.0;
+  bool fin = isfinite(rho) && isfinite(E);
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    fin = fin && isfinite(m[k]);
+    vel[k] = m[k] / rho;
+    q += vel[k] * vel[k];
+  }
+  q *= 0.5;
+  const double p = (gamma - 1.0) * (E - rho * q);
+  const double cs = sqrt(gamma * p / rho);
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) s += fabs(vel[k]) + cs;
+  if (!fin || !(rho > 0.0) || !(p > 0.0)) bad = true;
+  return s;
+}
+
+// Running maximum that lets a NaN win.
+__device__ __forceinline__ double nan_max(double acc, double s) { return (s != s || s > acc) ? s : acc; }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Fold one wave's CFL maximum and non-physical flag into the step control
+// word (one atomic per wave; a NaN maximum is raised to +inf so that it
+// wins).  Every lane of the wave must call it.
+__device__ __forceinline__ void cfl_commit_wave(StepCtl* ctl, double smax, bool bad) {
+  const bool nan = (smax != smax);
+  const double m = wave_max(nan ? __longlong_as_double(0x7ff0000000000000LL) : smax);
+  const unsigned long long anybad = __ballot(bad);
+  if ((threadIdx.x & 63) == 0) {
+    if (m > 0.0) atomicMax(&ctl->smax_bits, (unsigned long long)__double_as_longlong(m));
+    if (anybad) atomicOr(&ctl->status, 1u);
+  }
+}
+
 // ---------------------------------------------------------------- ghosts
 // Interior index for a line position k in [-3, n+2]; *flip = 1 when the
 // ghost is a mirror image whose normal momentum changes sign.

@@ -235,6 +235,8 @@ struct FusedArgs {
   int tiles_x, tiles_y;
   unsigned long long* list;  // cells next to a face that needs the WENO flux
   unsigned int* list_n;      // number of entries in list
+  StepCtl* cfl;              // RK: if set, fold the CFL speed of the new state
+                             // into cfl->smax_bits / status (next step's dt)
 };
 
 // Index of a line position clamped to [-3, n+2] and mapped through the
@@ -496,6 +498,8 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   double Fzp[NV];
   bool zprev = false;  // face z - 1/2 needs the nonlinear flux
   double upre[NV], hpre[NV];
+  double cfl_max = 0.0;  // CFL speed of the cells written here (a.cfl set)
+  bool cfl_bad = false;
   double unp[NV] = {};  // U^n of cell z (RK stages 2, 3), loaded a phase ahead
   if (owner) {
     double u[NV];
@@ -627,6 +631,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
         }
       }
       if (valid) {
+        double un[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const double dU = ((sfx[v][ix] - sfx[v][ix + 1]) + (sfy[v][iy] - sfy[v][iy + FT_X]) +
@@ -635,15 +640,23 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
             double r = a.rk_b * (r0.U[v] + dt * dU);
             if (a.rk_a != 0.0) r += a.rk_a * unp[v];
             a.out[v * g.ncell + off] = r;
+            un[v] = r;
           } else {
             a.out[v * g.ncell + off] = dU;
           }
+        }
+        // CFL speed of the new state; a listed cell is finished (and
+        // counted) by the correction kernel
+        if (OUT == OUT_RK && a.cfl != nullptr && cm == 0u) {
+          const double m[3] = {un[1], un[2], un[3]};
+          cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
         }
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fzp[v] = Fz[v];
     }
   }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
 // Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
@@ -698,6 +711,8 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
     scale = a.rk_b * dt;
   }
   const unsigned int n = *a.list_n;
+  double cfl_max = 0.0;
+  bool cfl_bad = false;
   for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const unsigned long long e = a.list[i];
     const long long off = (long long)(e >> 8);
@@ -720,9 +735,18 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += sg * dF[v];
     }
+    double un[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a.out[v * g.ncell + off] += scale * (acc[v] * ph.inv_dx);
+    for (int v = 0; v < NV; ++v) {
+      un[v] = a.out[v * g.ncell + off] + scale * (acc[v] * ph.inv_dx);
+      a.out[v * g.ncell + off] = un[v];
+    }
+    if (OUT == OUT_RK && a.cfl != nullptr) {
+      const double m[3] = {un[1], un[2], un[3]};
+      cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
+    }
   }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
 [[maybe_unused]] static __global__ void reset_list_kernel(unsigned int* list_n) {

@@ -19,6 +19,7 @@ FusedArgs make_args(const FusedLaunch& L) {
   a.zc = L.zc;
   a.list = L.list;
   a.list_n = &L.ctl->list_n;
+  a.cfl = L.out_kind == OUT_RK ? L.cfl : nullptr;
   a.tiles_x = (L.n[0] + FT_X - 1) / FT_X;
   a.tiles_y = (L.n[1] + FT_Y - 1) / FT_Y;
   return a;

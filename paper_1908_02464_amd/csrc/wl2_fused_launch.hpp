@@ -16,6 +16,7 @@ struct FusedLaunch {
   double* out;
   const double* Un;
   StepCtl* ctl;
+  StepCtl* cfl;  // RK stage: fold the CFL speed of the new state into it (or null)
   unsigned long long* list;
   double rk_a, rk_b;
   int out_kind;  // OUT_WRITE or OUT_RK

@@ -203,6 +203,52 @@ def test_3d_sweeps_path_parity(orc, capi, case):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("case", ["turb20x18x17", "turb16x12x10_mixed"])
+def test_3d_advance_folded_cfl(orc, capi, case):
+    """weno_l2is_advance on a 3D grid takes the CFL maximum of U^(n+1) from the
+    last stage kernels (and from the nonlinear-correction kernel for the
+    listed cells) instead of a separate reduction: every dt, and so U, must
+    be bit-identical to steps that reduce U each time; the clock and U match
+    the oracle's own steps."""
+    say(f"[advance-3d] case={case}")
+    import torch
+    U, dx, bc = make_case(case)
+    shape = shape_of(U)
+    po, pg = params_pair(orc, capi, shape, dx, bc=bc)
+    n = 12
+    # reference: one step per call (CFL reduced from U every time)
+    ctx = capi.Context(*shape, dx, G, pg)
+    A = to_dev(U)
+    t_ref = 0.0
+    for _ in range(n):
+        ctx.step(A)
+        t_ref += ctx.time()[1]
+    ctx.close()
+    ctx = capi.Context(*shape, dx, G, pg)
+    B = to_dev(U)
+    ctx.advance(B, n, 1e300)
+    t_adv, _, steps = ctx.clock()
+    assert ctx.status() == 0
+    ctx.close()
+    torch.cuda.synchronize()
+    a, b = to_host(A), to_host(B)
+    say(f"    t(step x{n}) = {t_ref!r}  t(advance) = {t_adv!r}  max|diff| = {np.abs(a - b).max():.3e}")
+    assert steps == n and t_adv == t_ref
+    assert np.array_equal(a, b)
+    # the oracle's own n CFL steps (its dt may drift from the GPU's by an ulp
+    # once the states differ by round-off)
+    Uo = U.copy()
+    t_o = 0.0
+    for _ in range(n):
+        dt_o, st = orc.step(Uo, dx, G, po)
+        assert st == 0
+        t_o += dt_o
+    err = z20(b, Uo)
+    say(f"    oracle: t={t_o!r} z20={err:.3e}")
+    assert abs(t_o - t_adv) <= 1e-13 * t_adv
+    assert err <= 1e-10
+
+
 def test_degenerate_tiny_grid(orc, capi):
     """Five cells, transmissive left and reflective right wall: one step to
     1e-12; after 100 steps the bound is four times the drift that a one-ulp
