@@ -563,10 +563,12 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
                    : "memory");
       load_col_raw<NV>(a.Uk, g, ocol, z + 4, upre);
       if (OUT == OUT_RK && a.rk_a != 0.0) {
-        // clamped column (equal to the cell's own index for valid owners)
+        // U^n and the output are streamed once (non-temporal), leaving L2 to
+        // the stage input, whose cells are also halo of the neighbour tiles.
+        // Clamped column (equal to the cell's own index for valid owners).
         const long long offn = ocol.xy + (long long)z * g.stride[2];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) unp[v] = a.Un[v * g.ncell + offn];
+        for (int v = 0; v < NV; ++v) unp[v] = __builtin_nontemporal_load(&a.Un[v * g.ncell + offn]);
       }
     }
     if (t < NHALO) {
@@ -639,10 +641,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
           if (OUT == OUT_RK) {
             double r = a.rk_b * (r0.U[v] + dt * dU);
             if (a.rk_a != 0.0) r += a.rk_a * unp[v];
-            a.out[v * g.ncell + off] = r;
+            __builtin_nontemporal_store(r, &a.out[v * g.ncell + off]);
             un[v] = r;
           } else {
-            a.out[v * g.ncell + off] = dU;
+            __builtin_nontemporal_store(dU, &a.out[v * g.ncell + off]);
           }
         }
         // CFL speed of the new state; a listed cell is finished (and
