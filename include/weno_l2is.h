@@ -144,13 +144,14 @@ int weno_l2is_face_debug(weno_l2is_ctx *ctx, const double *U, int dir,
  * clear != 0 resets the bits. */
 int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
 
-/* Kernel path and tuning of a context.  path: WL2_PATH_AUTO (fused
- * single-pass stage kernel for 3D grids, per-direction sweeps otherwise),
- * WL2_PATH_SWEEPS (per-direction sweeps everywhere), WL2_PATH_FUSED (fused
- * kernel; 3D only, else WL2_E_PARAM).  zchunk: z planes per workgroup of the
- * fused kernel (0 = automatic).  waves_per_simd: register budget of the
- * fused kernel, 1 or 2 (0 = default 2).  Results of all paths agree to
- * round-off. */
+/* Kernel path and tuning of a context.  path: WL2_PATH_AUTO or
+ * WL2_PATH_FUSED (the single-pass stage kernel of the grid's dimension: 3D
+ * column tiles marching in z, or 1D/2D rows of 63 cells marching in y),
+ * WL2_PATH_SWEEPS (one kernel per direction, partial sums through memory).
+ * zchunk: z planes (3D) or rows (2D, at most 62) per work item of the fused
+ * kernels (0 = automatic).  waves_per_simd: register budget of the 3D fused
+ * kernel, 1 or 2 (0 = default 2).  The two paths agree to round-off; the
+ * chunk and register budget change no result bit. */
 enum { WL2_PATH_AUTO = 0, WL2_PATH_SWEEPS = 1, WL2_PATH_FUSED = 2 };
 int weno_l2is_tune(weno_l2is_ctx *ctx, int path, int zchunk, int waves_per_simd);
 
@@ -173,14 +174,18 @@ void weno_l2is_destroy(weno_l2is_ctx *ctx);
 /* ------------------------------------------------------------------------
  * Batched and served form: many independent 1D/2D runs of uneven sizes
  * advanced together.  Each step is one replay of a captured hipGraph whose
- * persistent kernels walk ragged per-phase work tables over all admitted
- * runs; every run keeps its own CFL dt, clock (stopping exactly at its t_end)
- * and status.  A run's result is bit-identical to running it alone through
+ * persistent kernels walk tables of work items over all admitted runs (an
+ * item is 63 columns x a chunk of rows of one run: the unit of the
+ * single-grid 1D/2D stage kernel); every run keeps its own CFL dt, clock
+ * (stopping exactly at its t_end, or at a non-physical state) and status.  A
+ * run's result is bit-identical to running it alone through
  * weno_l2is_advance (same device code, same operation order).
  * The engine allocates `hbm_budget_bytes` once at creation and sub-allocates
  * runs from it: admission fails with WL2_E_BUDGET when a run's footprint
- * (3 state arrays, plus a partial-sum array in 2D) does not fit or all
- * `max_slots` slots are taken.  No device allocation happens while serving.
+ * (3 state arrays) does not fit or all `max_slots` slots are taken.  Beside
+ * the budget it holds a correction list of budget/72 entries of 8 bytes (one
+ * per admissible cell), the slot table and the work tables (which grow, with
+ * a new graph, when the admitted runs need more items than ever before).
  * LF splitting (WL2_SPLIT_LF) and 3D grids are not supported in a batch
  * (WL2_E_PARAM / WL2_E_SHAPE).
  * All calls are asynchronous on the engine's stream unless noted.
@@ -216,13 +221,13 @@ int weno_l2is_batch_fetch(weno_l2is_batch *b, int slot, double *U_out,
                           int out_on_host, double *t_out, unsigned *status,
                           unsigned *steps);
 
-/* Launch shape of the batched sweeps: `seg` cells per thread along a sweep
- * (4, 8 or 16; the pencil length) and `blocks` workgroups in the persistent
- * grid (64..65536); 0 keeps the current value.  Results do not depend on
- * either (every face is computed by the same arithmetic), only the speed
- * does; the captured graph is rebuilt on the next advance.  Returns
- * WL2_E_PARAM for values outside these sets. */
-int weno_l2is_batch_tune(weno_l2is_batch *b, int seg, int blocks);
+/* Launch shape of the batched stage kernels: `rows` rows per work item of a
+ * 2D run (1..62; a work item is 63 columns of one run, one wavefront) and
+ * `blocks` workgroups in the persistent grid (64..65536); 0 keeps the
+ * current value.  Results do not depend on either (every face is computed by
+ * the same arithmetic), only the speed does.  Returns WL2_E_PARAM for values
+ * outside these ranges. */
+int weno_l2is_batch_tune(weno_l2is_batch *b, int rows, int blocks);
 
 /* Bytes of the budget in use and number of admitted runs. */
 int weno_l2is_batch_usage(weno_l2is_batch *b, size_t *used_bytes,

@@ -3,9 +3,9 @@ keeps the fastest.  None of the shapes changes a result bit (every face is
 computed by the same arithmetic whatever thread computes it), so tuning is a
 pure speed choice.
 
-* Batched sweeps (1D/2D, many grids): pencil length `seg` (cells per thread
-  along a sweep) and the persistent grid size `blocks`, timed on a scratch
-  engine holding a sample of the workload.
+* Batched stage kernels (1D/2D, many grids): rows per work item of the 2D
+  runs and the persistent grid size `blocks`, timed on a scratch engine
+  holding a sample of the workload.
 * Fused 3D stage kernel (one grid): z planes per workgroup `zchunk` and the
   occupancy target `waves_per_simd`, timed on a scratch copy of the state.
 """
@@ -17,7 +17,7 @@ import torch
 
 from . import capi
 
-BATCH_SEGS = (4, 8, 16)
+BATCH_ROWS = (4, 8, 16, 32)
 BATCH_BLOCKS = (512, 1024, 2048, 4096, 8192)
 
 
@@ -34,10 +34,10 @@ def _time_batch(eng: capi.Batch, steps: int) -> float:
 
 
 def tune_batch(requests, budget_bytes: int, steps: int = 8, max_runs: int = 256,
-               segs=BATCH_SEGS, blocks=BATCH_BLOCKS, verbose: bool = False):
-    """Best (seg, blocks) for a mix shaped like `requests` (the first
+               rows=BATCH_ROWS, blocks=BATCH_BLOCKS, verbose: bool = False):
+    """Best (rows, blocks) for a mix shaped like `requests` (the first
     `max_runs` that fit the budget, run with an end time they never reach).
-    Returns (seg, blocks, {(seg, blocks): ms per step})."""
+    Returns (rows, blocks, {(rows, blocks): ms per step})."""
     eng = capi.Batch(budget_bytes, max(1, min(len(requests), max_runs)))
     n = 0
     for r in requests[:max_runs]:
@@ -47,11 +47,11 @@ def tune_batch(requests, budget_bytes: int, steps: int = 8, max_runs: int = 256,
         n += 1
     times = {}
     try:
-        for s, bl in itertools.product(segs, blocks):
-            eng.tune(s, bl)
-            times[(s, bl)] = _time_batch(eng, steps)
+        for r, bl in itertools.product(rows, blocks):
+            eng.tune(r, bl)
+            times[(r, bl)] = _time_batch(eng, steps)
             if verbose:
-                print(f"[autotune] batch seg={s} blocks={bl}: {times[(s, bl)]:.4f} ms/step "
+                print(f"[autotune] batch rows={r} blocks={bl}: {times[(r, bl)]:.4f} ms/step "
                       f"({n} runs)", flush=True)
     finally:
         eng.close()
@@ -62,8 +62,9 @@ def tune_batch(requests, budget_bytes: int, steps: int = 8, max_runs: int = 256,
 def tune_fused(nx: int, ny: int, nz: int, dx: float, U: torch.Tensor, gamma: float = 1.4,
                params: capi.Params | None = None, steps: int = 4,
                zchunks=(0, 16, 32, 64, 128), wpes=(1, 2), verbose: bool = False):
-    """Best (zchunk, waves_per_simd) of the fused 3D stage kernel for this
-    grid, timed on a scratch copy of U with a fixed dt.
+    """Best (zchunk, waves_per_simd) of the fused stage kernel for this grid
+    (zchunk: z planes in 3D, rows per item in 2D), timed on a scratch copy of
+    U with a fixed dt.
     Returns (zchunk, wpe, {(zchunk, wpe): ms per step})."""
     ctx = capi.Context(nx, ny, nz, dx, gamma, params)
     W = U.clone()
@@ -71,7 +72,7 @@ def tune_fused(nx: int, ny: int, nz: int, dx: float, U: torch.Tensor, gamma: flo
     times = {}
     try:
         for zc, w in itertools.product(zchunks, wpes):
-            if zc > nz:
+            if zc > (nz if nz > 1 else ny):
                 continue
             ctx.tune(capi.PATH_FUSED, zc, w)
             W.copy_(U)

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libweno_l2is.so")
-SOURCES = ["wl2_capi.hip", "wl2_batch.hip", "wl2_fused3d.hip"]
+SOURCES = ["wl2_capi.hip", "wl2_batch.hip", "wl2_fused3d.hip", "wl2_row.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

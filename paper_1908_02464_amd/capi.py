@@ -279,10 +279,10 @@ class Batch:
                                          C.byref(t), C.byref(st), C.byref(n)), "batch_fetch")
         return (U, t.value, st.value, n.value) if with_steps else (U, t.value, st.value)
 
-    def tune(self, seg: int = 0, blocks: int = 0):
-        """Pencil length (cells per thread) and persistent grid size of the
-        batched sweeps; 0 keeps the current value."""
-        _chk(lib().weno_l2is_batch_tune(self.h, int(seg), int(blocks)), "batch_tune")
+    def tune(self, rows: int = 0, blocks: int = 0):
+        """Rows per work item of the 2D runs and persistent grid size of the
+        batched stage kernels; 0 keeps the current value."""
+        _chk(lib().weno_l2is_batch_tune(self.h, int(rows), int(blocks)), "batch_tune")
 
     def usage(self):
         used, act = C.c_size_t(0), C.c_int(0)

@@ -2,7 +2,9 @@
 // pooled HBM budget with first-fit sub-allocation, slot table, ragged work
 // tables rebuilt on admission and retirement, and the per-step launch
 // sequence captured once in a hipGraph (the kernels read the tables from
-// device memory, so the graph stays valid while runs come and go).
+// device memory, so the graph stays valid while runs come and go; it is
+// captured again only when a table outgrows its buffer or the launch shape
+// changes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,7 +13,6 @@
 #include <vector>
 
 #include "../../include/weno_l2is.h"
-#include "wl2_aux.hpp"
 #include "wl2_batch.hpp"
 #include "wl2_desc.hpp"
 
@@ -20,7 +21,8 @@ using namespace wl2;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int SWEEP_BLOCKS_DEFAULT = 2048;  // persistent grid of the sweep kernels
+constexpr int ROW_BLOCKS_DEFAULT = 2048;  // persistent grid of the row kernels
+constexpr int ROWS_DEFAULT = 16;          // rows per work item of a 2D run
 constexpr int RED_BLOCKS = 1024;
 
 struct SlotInfo {
@@ -50,8 +52,9 @@ struct weno_l2is_batch {
   BGrid* h_grids = nullptr;
   StepCtl* d_ctl = nullptr;
   StepCtl* h_ctl = nullptr;  // staging for admission
-  BTable* d_tab = nullptr;   // [2]
-  BTable* h_tab = nullptr;
+  RowItem* d_items[2] = {nullptr, nullptr};  // work items of the 1D / 2D runs
+  RowItem* h_items[2] = {nullptr, nullptr};
+  int item_cap[2] = {0, 0};
   int chunk_cap = 0;
   int* d_cslot = nullptr;
   long long* d_cfirst = nullptr;
@@ -59,7 +62,9 @@ struct weno_l2is_batch {
   int* h_cslot = nullptr;
   long long* h_cfirst = nullptr;
   int* h_ccount = nullptr;
-  int* d_counts = nullptr;  // [0] = chunks, [1] = active slots
+  int* d_counts = nullptr;  // [0] chunks, [1] active slots, [2] 1D items, [3] 2D items
+  unsigned long long* d_list = nullptr;  // cells listed for the nonlinear correction
+  unsigned int* d_list_n = nullptr;
   int* h_counts = nullptr;
   int* d_slotlist = nullptr;
   int* h_slotlist = nullptr;
@@ -71,8 +76,8 @@ struct weno_l2is_batch {
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int seg = BATCH_SEG_DEFAULT;
-  int sweep_blocks = SWEEP_BLOCKS_DEFAULT;
+  int rows = ROWS_DEFAULT;
+  int row_blocks = ROW_BLOCKS_DEFAULT;
 };
 
 namespace {
@@ -114,28 +119,65 @@ hipError_t wait_upload(weno_l2is_batch* b) {
   return hipEventSynchronize(b->ev_upload);
 }
 
+void drop_graph(weno_l2is_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+// Item buffers of dimension index d (0: 1D, 1: 2D) for at least n items; a
+// new buffer invalidates the captured graph (its kernels hold the pointer).
+hipError_t reserve_items(weno_l2is_batch* b, int d, long long n) {
+  if (n <= b->item_cap[d]) return hipSuccess;
+  if (n > 0x3fffffffLL) return hipErrorInvalidValue;
+  long long cap = b->item_cap[d] > 0 ? b->item_cap[d] : 1024;
+  while (cap < n) cap *= 2;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return e;
+  b->upload_pending = false;
+  RowItem *dn = nullptr, *hn = nullptr;
+  if ((e = hipMalloc(&dn, sizeof(RowItem) * (size_t)cap)) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&hn, sizeof(RowItem) * (size_t)cap, 0)) != hipSuccess) {
+    (void)hipFree(dn);
+    return e;
+  }
+  (void)hipFree(b->d_items[d]);
+  (void)hipHostFree(b->h_items[d]);
+  b->d_items[d] = dn;
+  b->h_items[d] = hn;
+  b->item_cap[d] = (int)cap;
+  drop_graph(b);
+  return hipSuccess;
+}
+
 hipError_t upload_tables(weno_l2is_batch* b) {
   hipError_t e = wait_upload(b);
   if (e != hipSuccess) return e;
-  BTable* tx = &b->h_tab[0];
-  BTable* ty = &b->h_tab[1];
-  tx->n = ty->n = 0;
-  tx->total = ty->total = 0;
+  // sizes first (a buffer may have to grow)
+  long long need[2] = {0, 0};
+  for (int s = 0; s < b->max_slots; ++s) {
+    const SlotInfo& si = b->slots[s];
+    if (!si.used) continue;
+    const long long tiles = (si.n[0] + ROW_TILE - 1) / ROW_TILE;
+    if (si.dim == 1) need[0] += tiles;
+    else need[1] += tiles * ((si.n[1] + b->rows - 1) / b->rows);
+  }
+  for (int d = 0; d < 2; ++d)
+    if ((e = reserve_items(b, d, need[d] > 0 ? need[d] : 1)) != hipSuccess) return e;
+  int ni[2] = {0, 0};
   int nch = 0, nact = 0;
   for (int s = 0; s < b->max_slots; ++s) {
     const SlotInfo& si = b->slots[s];
     if (!si.used) continue;
     b->h_slotlist[nact++] = s;
-    const BGrid& G = b->h_grids[s];
-    tx->slot[tx->n] = s;
-    tx->start[tx->n] = tx->total;
-    tx->total += (G.nthr[0] + 63) / 64 * 64;
-    tx->n++;
-    if (si.dim == 2) {
-      ty->slot[ty->n] = s;
-      ty->start[ty->n] = ty->total;
-      ty->total += (G.nthr[1] + 63) / 64 * 64;
-      ty->n++;
+    for (int x0 = 0; x0 < si.n[0]; x0 += ROW_TILE) {
+      if (si.dim == 1) {
+        b->h_items[0][ni[0]++] = RowItem{s, x0, 0, 1};
+      } else {
+        for (int y0 = 0; y0 < si.n[1]; y0 += b->rows)
+          b->h_items[1][ni[1]++] = RowItem{s, x0, y0, std::min(y0 + b->rows, si.n[1])};
+      }
     }
     for (long long c0 = 0; c0 < si.ncell; c0 += BATCH_CHUNK) {
       if (nch >= b->chunk_cap) return hipErrorOutOfMemory;
@@ -145,17 +187,20 @@ hipError_t upload_tables(weno_l2is_batch* b) {
       ++nch;
     }
   }
-  tx->start[tx->n] = tx->total;
-  ty->start[ty->n] = ty->total;
   b->h_counts[0] = nch;
   b->h_counts[1] = nact;
+  b->h_counts[2] = ni[0];
+  b->h_counts[3] = ni[1];
   hipStream_t st = b->stream;
-  if ((e = hipMemcpyAsync(b->d_tab, b->h_tab, 2 * sizeof(BTable), hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(b->d_cslot, b->h_cslot, sizeof(int) * nch, hipMemcpyHostToDevice, st)) ||
+  for (int d = 0; d < 2; ++d)
+    if (ni[d] > 0 &&
+        (e = hipMemcpyAsync(b->d_items[d], b->h_items[d], sizeof(RowItem) * ni[d], hipMemcpyHostToDevice, st)))
+      return e;
+  if ((e = hipMemcpyAsync(b->d_cslot, b->h_cslot, sizeof(int) * nch, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(b->d_cfirst, b->h_cfirst, sizeof(long long) * nch, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(b->d_ccount, b->h_ccount, sizeof(int) * nch, hipMemcpyHostToDevice, st)) ||
       (e = hipMemcpyAsync(b->d_slotlist, b->h_slotlist, sizeof(int) * nact, hipMemcpyHostToDevice, st)) ||
-      (e = hipMemcpyAsync(b->d_counts, b->h_counts, 2 * sizeof(int), hipMemcpyHostToDevice, st)))
+      (e = hipMemcpyAsync(b->d_counts, b->h_counts, 4 * sizeof(int), hipMemcpyHostToDevice, st)))
     return e;
   if ((e = hipEventRecord(b->ev_upload, st)) != hipSuccess) return e;
   b->upload_pending = true;
@@ -164,23 +209,7 @@ hipError_t upload_tables(weno_l2is_batch* b) {
   return hipSuccess;
 }
 
-void set_segments(const weno_l2is_batch* b, BGrid& G) {
-  const int nx = G.g.n[0], ny = G.g.n[1];
-  G.nseg[0] = (nx + b->seg - 1) / b->seg;
-  G.nseg[1] = (ny + b->seg - 1) / b->seg;
-  G.nthr[0] = (long long)G.nseg[0] * ny;
-  G.nthr[1] = G.dim == 2 ? (long long)G.nseg[1] * nx : 0;
-}
-
-template <int SEG>
-void enqueue_sweeps(weno_l2is_batch* b, int stage) {
-  hipLaunchKernelGGL((batch_sweep_kernel<0, SEG>), dim3(b->sweep_blocks), dim3(SWEEP_BLOCK), 0,
-                     b->stream, b->d_grids, b->d_tab + 0, stage);
-  hipLaunchKernelGGL((batch_sweep_kernel<1, SEG>), dim3(b->sweep_blocks), dim3(SWEEP_BLOCK), 0,
-                     b->stream, b->d_grids, b->d_tab + 1, stage);
-}
-
-// The launch sequence of one batched SSP-RK3 step.
+// The launch sequence of one batched SSP-RK3 step (item buffers exist).
 hipError_t enqueue_step(weno_l2is_batch* b) {
   hipStream_t st = b->stream;
   BChunks ch{0, 0, b->d_cslot, b->d_cfirst, b->d_ccount};
@@ -189,17 +218,23 @@ hipError_t enqueue_step(weno_l2is_batch* b) {
   hipLaunchKernelGGL(batch_finalize_kernel, dim3(16), dim3(256), 0, st, b->d_grids, b->d_slotlist,
                      b->d_counts + 1);
   for (int stage = 0; stage < 3; ++stage) {
-    switch (b->seg) {
-      case 4: enqueue_sweeps<4>(b, stage); break;
-      case 16: enqueue_sweeps<16>(b, stage); break;
-      default: enqueue_sweeps<8>(b, stage); break;
-    }
+    hipLaunchKernelGGL(row_list_reset_kernel, dim3(1), dim3(64), 0, st, b->d_list_n);
+    hipLaunchKernelGGL(batch_row_kernel<3>, dim3(b->row_blocks), dim3(RW), 0, st, b->d_grids,
+                       b->d_items[0], b->d_counts + 2, stage, b->d_list, b->d_list_n);
+    hipLaunchKernelGGL(batch_row_kernel<4>, dim3(b->row_blocks), dim3(RW), 0, st, b->d_grids,
+                       b->d_items[1], b->d_counts + 3, stage, b->d_list, b->d_list_n);
+    hipLaunchKernelGGL(batch_fix_kernel, dim3(1024), dim3(128), 0, st, b->d_grids, b->d_list,
+                       b->d_list_n, stage);
   }
   return hipGetLastError();
 }
 
 hipError_t ensure_graph(weno_l2is_batch* b) {
   if (b->gexec) return hipSuccess;
+  for (int d = 0; d < 2; ++d) {  // buffers exist before the capture
+    hipError_t e = reserve_items(b, d, 1);
+    if (e != hipSuccess) return e;
+  }
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   hipError_t e2 = enqueue_step(b);
@@ -236,32 +271,36 @@ int weno_l2is_batch_create(size_t hbm_budget_bytes, int max_slots, void* hip_str
   b->slots.resize(max_slots);
   // every chunk covers at least one 3-variable cell of 3 arrays (72 bytes)
   b->chunk_cap = (int)std::min<size_t>((size_t)1 << 26, b->budget / (72 * BATCH_CHUNK) + max_slots + 16);
+  // a list entry per admissible cell (at least 72 bytes of state each)
+  const size_t list_cap = b->budget / 72 + 1;
   bool ok = hipMalloc(&b->pool, b->budget) == hipSuccess &&
+            hipMalloc(&b->d_list, sizeof(unsigned long long) * list_cap) == hipSuccess &&
+            hipMalloc(&b->d_list_n, sizeof(unsigned int)) == hipSuccess &&
             hipMalloc(&b->d_grids, sizeof(BGrid) * max_slots) == hipSuccess &&
             hipMalloc(&b->d_ctl, sizeof(StepCtl) * max_slots) == hipSuccess &&
-            hipMalloc(&b->d_tab, 2 * sizeof(BTable)) == hipSuccess &&
             hipMalloc(&b->d_cslot, sizeof(int) * b->chunk_cap) == hipSuccess &&
             hipMalloc(&b->d_cfirst, sizeof(long long) * b->chunk_cap) == hipSuccess &&
             hipMalloc(&b->d_ccount, sizeof(int) * b->chunk_cap) == hipSuccess &&
-            hipMalloc(&b->d_counts, 2 * sizeof(int)) == hipSuccess &&
+            hipMalloc(&b->d_counts, 4 * sizeof(int)) == hipSuccess &&
             hipMalloc(&b->d_slotlist, sizeof(int) * max_slots) == hipSuccess &&
             hipMalloc(&b->d_state, sizeof(SlotState) * max_slots) == hipSuccess &&
             hipHostMalloc(&b->h_grids, sizeof(BGrid) * max_slots, 0) == hipSuccess &&
             hipHostMalloc(&b->h_ctl, sizeof(StepCtl) * max_slots, 0) == hipSuccess &&
-            hipHostMalloc(&b->h_tab, 2 * sizeof(BTable), 0) == hipSuccess &&
             hipHostMalloc(&b->h_cslot, sizeof(int) * b->chunk_cap, 0) == hipSuccess &&
             hipHostMalloc(&b->h_cfirst, sizeof(long long) * b->chunk_cap, 0) == hipSuccess &&
             hipHostMalloc(&b->h_ccount, sizeof(int) * b->chunk_cap, 0) == hipSuccess &&
-            hipHostMalloc(&b->h_counts, 2 * sizeof(int), 0) == hipSuccess &&
+            hipHostMalloc(&b->h_counts, 4 * sizeof(int), 0) == hipSuccess &&
             hipHostMalloc(&b->h_slotlist, sizeof(int) * max_slots, 0) == hipSuccess &&
             hipHostMalloc(&b->h_state, sizeof(SlotState) * max_slots, 0) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_state, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_upload, hipEventDisableTiming) == hipSuccess;
   if (ok) {
     b->free_list.emplace_back(0, b->budget);
-    std::memset(b->h_tab, 0, 2 * sizeof(BTable));
+    std::memset(b->h_counts, 0, 4 * sizeof(int));
     std::memset(b->h_grids, 0, sizeof(BGrid) * max_slots);
     ok = hipMemcpyAsync(b->d_grids, b->h_grids, sizeof(BGrid) * max_slots, hipMemcpyHostToDevice,
+                        b->stream) == hipSuccess &&
+         hipMemcpyAsync(b->d_counts, b->h_counts, 4 * sizeof(int), hipMemcpyHostToDevice,
                         b->stream) == hipSuccess &&
          hipStreamSynchronize(b->stream) == hipSuccess;
   }
@@ -298,7 +337,7 @@ int weno_l2is_batch_admit(weno_l2is_batch* b, int nx, int ny, int nz, double dx,
   si.nvar = si.dim + 2;
   si.ncell = (long long)nx * ny;
   const size_t arr = round_up(sizeof(double) * (size_t)si.nvar * si.ncell);
-  si.bytes = arr * (si.dim == 2 ? 4 : 3);
+  si.bytes = arr * 3;
   if (!pool_alloc(b, si.bytes, &si.off)) return WL2_E_BUDGET;
   hipError_t e = wait_upload(b);
   if (e != hipSuccess) {
@@ -312,12 +351,10 @@ int weno_l2is_batch_admit(weno_l2is_batch* b, int nx, int ny, int nz, double dx,
   G.U = (double*)base;
   G.U1 = (double*)(base + arr);
   G.U2 = (double*)(base + 2 * arr);
-  G.acc = si.dim == 2 ? (double*)(base + 3 * arr) : nullptr;
   G.ctl = b->d_ctl + s;
   G.cfl_dx = p->cfl * dx;
   G.dim = si.dim;
   G.nv = si.nvar;
-  set_segments(b, G);
   G.active = 1;
   StepCtl& C = b->h_ctl[s];
   std::memset(&C, 0, sizeof(C));
@@ -418,30 +455,18 @@ int weno_l2is_batch_fetch(weno_l2is_batch* b, int slot, double* U_out, int out_o
   return WL2_OK;
 }
 
-int weno_l2is_batch_tune(weno_l2is_batch* b, int seg, int blocks) {
+int weno_l2is_batch_tune(weno_l2is_batch* b, int rows, int blocks) {
   if (!b) return WL2_E_NULL;
-  if (seg != 0 && seg != 4 && seg != 8 && seg != 16) return WL2_E_PARAM;
+  if (rows < 0 || rows > ROW_MAX_YCH) return WL2_E_PARAM;
   if (blocks != 0 && (blocks < 64 || blocks > 65536)) return WL2_E_PARAM;
-  const int new_seg = seg ? seg : b->seg;
-  const int new_blocks = blocks ? blocks : b->sweep_blocks;
-  if (new_seg == b->seg && new_blocks == b->sweep_blocks) return WL2_OK;
-  hipError_t e = wait_upload(b);
-  if (e != hipSuccess) return WL2_E_HIP;
-  b->seg = new_seg;
-  b->sweep_blocks = new_blocks;
-  // segment counts of the admitted runs follow the pencil length
-  for (int s = 0; s < b->max_slots; ++s)
-    if (b->slots[s].used) set_segments(b, b->h_grids[s]);
-  if ((e = hipMemcpyAsync(b->d_grids, b->h_grids, sizeof(BGrid) * b->max_slots,
-                          hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
-      (e = hipEventRecord(b->ev_upload, b->stream)) != hipSuccess)
-    return WL2_E_HIP;
-  b->upload_pending = true;
-  b->dirty = true;  // work tables depend on the segment counts
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->gexec = nullptr;
-  b->graph = nullptr;
+  if (rows && rows != b->rows) {
+    b->rows = rows;
+    b->dirty = true;  // the 2D items follow the rows per item
+  }
+  if (blocks && blocks != b->row_blocks) {
+    b->row_blocks = blocks;
+    drop_graph(b);  // the grid size is part of the captured launches
+  }
   return WL2_OK;
 }
 
@@ -460,9 +485,14 @@ void weno_l2is_batch_destroy(weno_l2is_batch* b) {
   if (b->ev_state) (void)hipEventDestroy(b->ev_state);
   if (b->ev_upload) (void)hipEventDestroy(b->ev_upload);
   (void)hipFree(b->pool);
+  (void)hipFree(b->d_list);
+  (void)hipFree(b->d_list_n);
   (void)hipFree(b->d_grids);
   (void)hipFree(b->d_ctl);
-  (void)hipFree(b->d_tab);
+  for (int d = 0; d < 2; ++d) {
+    (void)hipFree(b->d_items[d]);
+    (void)hipHostFree(b->h_items[d]);
+  }
   (void)hipFree(b->d_cslot);
   (void)hipFree(b->d_cfirst);
   (void)hipFree(b->d_ccount);
@@ -471,7 +501,6 @@ void weno_l2is_batch_destroy(weno_l2is_batch* b) {
   (void)hipFree(b->d_state);
   (void)hipHostFree(b->h_grids);
   (void)hipHostFree(b->h_ctl);
-  (void)hipHostFree(b->h_tab);
   (void)hipHostFree(b->h_cslot);
   (void)hipHostFree(b->h_cfirst);
   (void)hipHostFree(b->h_ccount);

@@ -1,11 +1,14 @@
 // Batched form: many independent 1D/2D grids advanced by persistent kernels
-// walking ragged work tables (one table per sweep phase), so a fixed launch
+// walking tables of work items (one table per dimension), so a fixed launch
 // shape serves any mix of grid sizes and the per-step launch sequence can be
-// captured once in a hipGraph.  Every grid runs exactly the per-segment code
-// of the single-grid path (sweep_body), with its own dt, clock and status, so
-// its result is bit-identical to running it alone.
+// captured once in a hipGraph.  A work item is the unit of the single-grid
+// row kernel (63 columns x a chunk of rows of one grid, one wavefront) and
+// runs exactly its code (row_item), with the grid's own dt, clock and
+// status, so a run's result is bit-identical to running it alone.
 #pragma once
-#include "wl2_kernels.hpp"
+#include "wl2_aux.hpp"
+#include "wl2_row.hpp"
+#include "wl2_row_launch.hpp"
 
 namespace wl2 {
 
@@ -13,32 +16,23 @@ namespace wl2 {
 struct BGrid {
   KGrid g;
   KPhys ph;
-  double* U;    // state U^n, updated in place by the third stage
-  double* U1;   // stage buffers
+  double* U;   // state U^n, updated in place by the third stage
+  double* U1;  // stage buffers
   double* U2;
-  double* acc;  // 2D: x-sweep partial sum
   StepCtl* ctl;
   double cfl_dx;
   int dim, nv;
-  int nseg[2];        // segments per line along x and y
-  long long nthr[2];  // threads of the x and y sweeps
   int active;
   int pad;
 };
 
-constexpr int BATCH_SEG_DEFAULT = 8;
 constexpr int BATCH_MAX_SLOTS = 4096;
 constexpr int BATCH_CHUNK = 4096;  // cells per reduction chunk
 
-// Ragged table of one phase: entry k covers global work items
-// [start[k], start[k+1]) of slot slot[k]; starts are multiples of 64 so that
-// a wavefront never mixes two grids.
-struct BTable {
-  int n;
-  int pad;
-  long long total;
-  int slot[BATCH_MAX_SLOTS];
-  long long start[BATCH_MAX_SLOTS + 1];
+// Work item of the batched row kernel: columns x0 .. x0+62 and rows y0 .. y1-1
+// of the grid in `slot`.
+struct RowItem {
+  int slot, x0, y0, y1;
 };
 
 // Reduction chunks: chunk c covers cells [first[c], first[c] + count[c]) of
@@ -51,48 +45,73 @@ struct BChunks {
   int* count;
 };
 
-__device__ __forceinline__ int table_find(const BTable* t, long long i) {
-  int lo = 0, hi = t->n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (t->start[mid] <= i) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+// Stage `stage` of every item of one dimension (NV = 3: 1D runs, 4: 2D).
+// Stage pointers and RK coefficients of a run.
+struct StageRefs {
+  const double* Uk;
+  double* out;
+  double ra, rb;
+};
+
+__device__ __forceinline__ StageRefs stage_refs(const BGrid& G, int stage) {
+  StageRefs r;
+  r.Uk = stage == 0 ? G.U : (stage == 1 ? G.U1 : G.U2);
+  r.out = stage == 0 ? G.U1 : (stage == 1 ? G.U2 : G.U);
+  r.ra = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+  r.rb = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+  return r;
 }
 
-// PH = 0: x sweeps of all grids (1D: with the RK combination; 2D: into acc);
-// PH = 1: y sweeps of the 2D grids (with the RK combination).  SEG cells per
-// thread along the sweep (BGrid::nseg was computed for the same SEG).
-template <int PH, int SEG>
-__global__ __launch_bounds__(SWEEP_BLOCK) void batch_sweep_kernel(const BGrid* __restrict__ grids,
-                                                                  const BTable* __restrict__ tab,
-                                                                  int stage) {
-  const long long total = tab->total;
-  for (long long i = (long long)blockIdx.x * SWEEP_BLOCK + threadIdx.x; i < total;
-       i += (long long)gridDim.x * SWEEP_BLOCK) {
-    const int k = table_find(tab, i);
-    const BGrid& G = grids[tab->slot[k]];
-    const long long gid = i - tab->start[k];
-    if (gid >= G.nthr[PH]) continue;  // wavefront padding
-    if (!(G.ctl->dt > 0.0)) continue;  // finished (or not started) run
-    const double* Uk = stage == 0 ? G.U : (stage == 1 ? G.U1 : G.U2);
-    double* out = stage == 0 ? G.U1 : (stage == 1 ? G.U2 : G.U);
-    const double ra = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
-    const double rb = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+template <int NV>
+__global__ __launch_bounds__(RW, 2) void batch_row_kernel(const BGrid* __restrict__ grids,
+                                                         const RowItem* __restrict__ items,
+                                                         const int* n_items, int stage,
+                                                         unsigned long long* list,
+                                                         unsigned int* list_n) {
+  __shared__ double buf[NV + 3][RB];
+  __shared__ double ring[2][NV + 3][RW];
+  const int n = *n_items;
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const RowItem it = items[k];
+    const BGrid& G = grids[it.slot];
+    const double dt = G.ctl->dt;
+    if (!(dt > 0.0)) continue;  // finished (or not started) run
+    const StageRefs sr = stage_refs(G, stage);
+    const RowArgs a{sr.Uk, sr.out, G.U, G.ctl, sr.ra, sr.rb, list, list_n,
+                    (unsigned long long)it.slot << 40};
+    if (G.ph.split == SPLIT_LLF && G.ph.hybrid == HYB_PER_FIELD)
+      row_item<NV, OUT_RK, 0, 0>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
+    else
+      row_item<NV, OUT_RK, -1, -1>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
+  }
+}
+
+// Nonlinear corrections of the cells listed in this stage by all runs
+// (entries slot << 40 | element offset << 8 | face mask): FIX_GRP lanes per
+// entry for a short list, a lane per entry for a long one (same bits).
+__global__ __launch_bounds__(128) void batch_fix_kernel(const BGrid* __restrict__ grids,
+                                                        const unsigned long long* __restrict__ list,
+                                                        const unsigned int* list_n, int stage) {
+  const unsigned int n = *list_n;
+  const unsigned int threads = gridDim.x * blockDim.x;
+  const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool grouped = n <= threads / FIX_GRP;
+  const unsigned int step = grouped ? threads / FIX_GRP : threads;
+  for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
+    const unsigned long long e = list[i];
+    const BGrid& G = grids[(int)(e >> 40)];
+    const double dt = G.ctl->dt;
+    if (!(dt > 0.0)) continue;
+    const StageRefs sr = stage_refs(G, stage);
+    const long long off = (long long)((e >> 8) & 0xffffffffull);
+    const unsigned cm = (unsigned)(e & 0xffu);
+    const bool fast = G.ph.split == SPLIT_LLF && G.ph.hybrid == HYB_PER_FIELD;
     if (G.dim == 1) {
-      if (PH == 0) {
-        SweepArgs a{Uk, out, nullptr, G.U, G.ctl, ra, rb};
-        sweep_body<3, 0, SEG, OUT_RK>(a, G.g, G.ph, G.nseg[0], gid);
-      }
+      if (fast) row_fix_cell<3, 0, 0>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
+      else row_fix_cell<3, -1, -1>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
     } else {
-      if (PH == 0) {
-        SweepArgs a{Uk, G.acc, nullptr, nullptr, G.ctl, 0.0, 1.0};
-        sweep_body<4, 0, SEG, OUT_WRITE>(a, G.g, G.ph, G.nseg[0], gid);
-      } else {
-        SweepArgs a{Uk, out, G.acc, G.U, G.ctl, ra, rb};
-        sweep_body<4, 1, SEG, OUT_RK>(a, G.g, G.ph, G.nseg[1], gid);
-      }
+      if (fast) row_fix_cell<4, 0, 0>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
+      else row_fix_cell<4, -1, -1>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
     }
   }
 }

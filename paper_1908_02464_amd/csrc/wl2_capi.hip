@@ -15,6 +15,7 @@
 #include "wl2_aux.hpp"
 #include "wl2_desc.hpp"
 #include "wl2_fused_launch.hpp"
+#include "wl2_row_launch.hpp"
 #include "wl2_kernels.hpp"
 
 using namespace wl2;
@@ -30,7 +31,7 @@ struct weno_l2is_ctx {
   double* U1;
   double* U2;
   double* acc;
-  unsigned long long* list;  // 3D: cells next to faces needing the WENO flux
+  unsigned long long* list;  // cells next to faces needing the WENO flux (fused kernels)
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
@@ -171,6 +172,47 @@ hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
 }
 
 bool use_fused(const weno_l2is_ctx* c) { return c->dim == 3 && c->path != WL2_PATH_SWEEPS; }
+bool use_row(const weno_l2is_ctx* c) { return c->dim <= 2 && c->path != WL2_PATH_SWEEPS; }
+
+// Rows per work item of the 1D/2D kernel: the tuned value, else the largest
+// of 32, 16, 8, 4 that still gives >= 2048 items (two per SIMD).
+int row_ych(const weno_l2is_ctx* c) {
+  if (c->dim == 1) return 1;
+  const int cap = ROW_MAX_YCH < c->n[1] ? ROW_MAX_YCH : c->n[1];
+  if (c->zchunk > 0) return c->zchunk < cap ? c->zchunk : cap;
+  const long long tiles = (c->n[0] + ROW_TILE - 1) / ROW_TILE;
+  int y = 32 < cap ? 32 : cap;
+  while (y > 4 && tiles * ((c->n[1] + y - 1) / y) < 2048) y /= 2;
+  return y;
+}
+
+hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
+                      const double* Un, double ra, double rb) {
+  RowLaunch L;
+  L.Uk = Uk;
+  L.out = out;
+  L.Un = Un;
+  L.ctl = c->ctl;
+  L.rk_a = ra;
+  L.rk_b = rb;
+  L.out_kind = out_kind;
+  L.ych = row_ych(c);
+  L.fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
+  L.nvar = c->nvar;
+  L.list = c->list;
+  L.list_n = &c->ctl->list_n;
+  L.g = c->g;
+  L.ph = c->ph;
+  L.stream = c->stream;
+  hipError_t e = row_reset(L);
+  if (e != hipSuccess) return e;
+  {
+    TimedLaunch tl(c, out_kind == OUT_RK ? "row_rk" : "row_rhs");
+    if ((e = row_launch(L)) != hipSuccess) return e;
+  }
+  TimedLaunch tl(c, "row_fix");
+  return row_fix(L);
+}
 
 int fused_zchunk(const weno_l2is_ctx* c) {
   if (c->zchunk > 0) return c->zchunk < c->n[2] ? c->zchunk : c->n[2];
@@ -218,6 +260,7 @@ hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
   hipError_t e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
+  if (use_row(c)) return launch_row(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
   for (int d = 0; d < c->dim; ++d) {
     SweepArgs a{Uk, out, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -232,6 +275,7 @@ hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, dou
   hipError_t e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
+  if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb);
   for (int d = 0; d < c->dim - 1; ++d) {
     SweepArgs a{Uk, c->acc, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -301,8 +345,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   bool ok = hipMalloc(&c->U1, bytes) == hipSuccess && hipMalloc(&c->U2, bytes) == hipSuccess &&
             hipMalloc(&c->acc, bytes) == hipSuccess &&
             hipMalloc(&c->ctl, sizeof(StepCtl)) == hipSuccess;
-  if (ok && c->dim == 3)
-    ok = hipMalloc(&c->list, sizeof(unsigned long long) * (size_t)c->ncell) == hipSuccess;
+  if (ok) ok = hipMalloc(&c->list, sizeof(unsigned long long) * (size_t)c->ncell) == hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->U1);
@@ -466,7 +509,7 @@ int weno_l2is_tune(weno_l2is_ctx* c, int path, int zchunk, int waves_per_simd) {
   if (!c) return WL2_E_NULL;
   if (path < WL2_PATH_AUTO || path > WL2_PATH_FUSED || zchunk < 0) return WL2_E_PARAM;
   if (waves_per_simd < 0 || waves_per_simd > 2) return WL2_E_PARAM;
-  if (path == WL2_PATH_FUSED && !(c->dim == 3 && c->nvar == 5)) return WL2_E_PARAM;
+
   c->path = path;
   c->zchunk = zchunk;
   c->wpe = waves_per_simd == 0 ? 2 : waves_per_simd;

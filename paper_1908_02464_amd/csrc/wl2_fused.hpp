@@ -17,8 +17,8 @@
 // round-robin over the 8 XCDs) take a contiguous range of tiles and share
 // their halos in that XCD's L2.
 #pragma once
-#include "wl2_device.hpp"
 #include "wl2_fused_launch.hpp"
+#include "wl2_lface.hpp"
 
 namespace wl2 {
 
@@ -29,197 +29,6 @@ constexpr int FP_N = FP_X * FP_Y;
 constexpr int NXF = (FT_X + 1) * FT_Y;           // 255 x faces per plane
 constexpr int NYF = FT_X * (FT_Y + 1);           // 256 y faces per plane
 constexpr int NHALO = 6 * FT_Y + 6 * FT_X;       // 186 halo cells per plane
-
-// 1/x and 1/sqrt(x) from the hardware seeds refined by two Newton steps (the
-// seed error squares each step; the result is within a few ulp, not
-// correctly rounded).
-__device__ __forceinline__ double fast_rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-  }
-  return r;
-}
-
-__device__ __forceinline__ double fast_rsqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-  }
-  return y;
-}
-
-template <int NV>
-struct LRec {
-  double U[NV];
-  double p, c, iw;  // pressure, sound speed, 1/sqrt(rho)
-};
-
-template <int NV>
-__device__ __forceinline__ void make_lrec(const double (&u)[NV], const KPhys& ph, LRec<NV>& r) {
-  constexpr int DIM = NV - 2;
-  const double iw = fast_rsqrt(u[0]);
-  const double ir = iw * iw;
-  double m2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
-  const double p = ph.gm1 * (u[NV - 1] - 0.5 * ir * m2);
-  const double c2 = ph.gamma * p * ir;
-  r.c = c2 * fast_rsqrt(c2);
-  r.p = p;
-  r.iw = iw;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) r.U[v] = u[v];
-}
-
-// Flux along DIR and normal velocity from a light record.
-template <int NV, int DIR>
-__device__ __forceinline__ void lflux(const LRec<NV>& r, double (&F)[NV], double& un) {
-  constexpr int DIM = NV - 2;
-  un = r.U[1 + DIR] * (r.iw * r.iw);
-  F[0] = r.U[1 + DIR];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) F[1 + k] = un * r.U[1 + k] + (k == DIR ? r.p : 0.0);
-  F[NV - 1] = (r.U[NV - 1] + r.p) * un;
-}
-
-template <int NV, int DIR>
-__device__ __forceinline__ void to_cellrec(const LRec<NV>& r, CellRec<NV>& c) {
-#pragma unroll
-  for (int v = 0; v < NV; ++v) c.U[v] = r.U[v];
-  lflux<NV, DIR>(r, c.F, c.un);
-  c.c = r.c;
-  c.iw = r.iw;
-  c.p = r.p;
-}
-
-template <int NV, int DIR>
-__device__ __forceinline__ void roe_light(const LRec<NV>& L, const LRec<NV>& R, const KPhys& ph,
-                                          Roe<NV>& s) {
-  constexpr int DIM = NV - 2;
-  const double wl = L.U[0] * L.iw, wr = R.U[0] * R.iw;
-  const double is = fast_rcp(wl + wr);
-  double q = 0.0;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    s.u[k] = (L.U[1 + k] * L.iw + R.U[1 + k] * R.iw) * is;
-    q += s.u[k] * s.u[k];
-  }
-  s.q = 0.5 * q;
-  s.H = ((L.U[NV - 1] + L.p) * L.iw + (R.U[NV - 1] + R.p) * R.iw) * is;
-  const double c2 = ph.gm1 * (s.H - s.q);
-  s.ic = fast_rsqrt(c2);
-  s.c = c2 * s.ic;
-  s.b1 = ph.gm1 * s.ic * s.ic;
-  s.b2 = s.b1 * s.q;
-  s.irho = L.iw * R.iw;
-}
-
-// Linear-branch flux of one face from six light records; returns the mask
-// of fields whose detector asks for the nonlinear flux.
-// `src.get(m, rec)` supplies stencil cell m = 0..5 (j-2 .. j+3); cells are
-// requested in the pairs (0,5), (1,4), (2,3) so only two are live at a time.
-// SPLIT / HYB: compile-time splitting and switch modes, or -1 to read them
-// from ph at run time.
-template <int NV, int DIR, int SPLIT, int HYB, class Src>
-__device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& ph, double eps_thr,
-                                                  const unsigned long long* lfb, double (&Fh)[NV]) {
-  const int split = SPLIT >= 0 ? SPLIT : ph.split;
-  const int hybrid = HYB >= 0 ? HYB : ph.hybrid;
-  double dU5[NV], Fc6[NV];
-  double am, a0, ap;
-  LRec<NV> c2, c3;
-  {
-    LRec<NV> c0, c5;
-    src.get(0, c0);
-    src.get(5, c5);
-    double F0[NV], F5[NV], u0, u5;
-    lflux<NV, DIR>(c0, F0, u0);
-    lflux<NV, DIR>(c5, F5, u5);
-    am = fmax(fabs(u0 - c0.c), fabs(u5 - c5.c));
-    a0 = fmax(fabs(u0), fabs(u5));
-    ap = fmax(fabs(u0 + c0.c), fabs(u5 + c5.c));
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      dU5[i] = c0.U[i] - c5.U[i];
-      Fc6[i] = F0[i] + F5[i];
-    }
-  }
-  {
-    LRec<NV> c1, c4;
-    src.get(1, c1);
-    src.get(4, c4);
-    double F1[NV], F4[NV], u1, u4;
-    lflux<NV, DIR>(c1, F1, u1);
-    lflux<NV, DIR>(c4, F4, u4);
-    am = fmax(am, fmax(fabs(u1 - c1.c), fabs(u4 - c4.c)));
-    a0 = fmax(a0, fmax(fabs(u1), fabs(u4)));
-    ap = fmax(ap, fmax(fabs(u1 + c1.c), fabs(u4 + c4.c)));
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      dU5[i] += 5.0 * (c4.U[i] - c1.U[i]);
-      Fc6[i] -= 8.0 * (F1[i] + F4[i]);
-    }
-  }
-  src.get(2, c2);
-  src.get(3, c3);
-  {
-    double F2[NV], F3[NV], u2, u3;
-    lflux<NV, DIR>(c2, F2, u2);
-    lflux<NV, DIR>(c3, F3, u3);
-    am = fmax(am, fmax(fabs(u2 - c2.c), fabs(u3 - c3.c)));
-    a0 = fmax(a0, fmax(fabs(u2), fabs(u3)));
-    ap = fmax(ap, fmax(fabs(u2 + c2.c), fabs(u3 + c3.c)));
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      dU5[i] += 10.0 * (c2.U[i] - c3.U[i]);
-      Fc6[i] = (Fc6[i] + 37.0 * (F2[i] + F3[i])) * (1.0 / 60.0);
-    }
-  }
-  Roe<NV> s;
-  roe_light<NV, DIR>(c2, c3, ph, s);
-  double a[NV];
-  if (split == SPLIT_LLF) {
-    a[0] = am;
-#pragma unroll
-    for (int k = 1; k < NV - 1; ++k) a[k] = a0;
-    a[NV - 1] = ap;
-  } else if (split == SPLIT_ROE) {
-    a[0] = fabs(s.u[DIR] - s.c);
-#pragma unroll
-    for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
-    a[NV - 1] = fabs(s.u[DIR] + s.c);
-  } else {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] = __longlong_as_double((long long)lfb[k]);
-  }
-  double dv[NV], d[NV];
-  project<NV, DIR>(s, dU5, dv);
-  unsigned weno = 0;
-  double smax = 0.0;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    dv[k] *= (1.0 / 60.0);
-    const double t = dv[k] * s.irho;
-    const double sig = t * t;  // Eq.(30)
-    smax = fmax(smax, sig);
-    if (!(sig < eps_thr)) weno |= 1u << k;
-    d[k] = a[k] * dv[k];
-  }
-  if (hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
-  else if (hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
-  else if (hybrid == HYB_LINEAR_ONLY) weno = 0u;
-  double Rd[NV];
-  back_project<NV, DIR>(s, d, Rd);
-#pragma unroll
-  for (int i = 0; i < NV; ++i) Fh[i] = Fc6[i] + Rd[i];
-  return weno;
-}
 
 struct V5 {
   double v[5];
@@ -239,13 +48,6 @@ struct FusedArgs {
                              // into cfl->smax_bits / status (next step's dt)
 };
 
-// Index of a line position clamped to [-3, n+2] and mapped through the
-// boundary rule; flip set for mirror ghosts.
-__device__ __forceinline__ int ghost_clamped(int k, int n, int lo, int hi, bool& flip) {
-  k = k < -3 ? -3 : (k > n + 2 ? n + 2 : k);
-  return ghost_index(k, n, lo, hi, flip);
-}
-
 template <int NV>
 __device__ __forceinline__ void lds_put(double (*srec)[FP_N], int idx, const LRec<NV>& r) {
 #pragma unroll
@@ -264,15 +66,7 @@ __device__ __forceinline__ void lds_get(double (*srec)[FP_N], int idx, LRec<NV>&
   r.iw = srec[NV + 2][idx];
 }
 
-// Stencil accessors for face_linear_l.
-template <int NV>
-struct WinSrc {  // the owner's z window (registers)
-  const LRec<NV>&w0, &w1, &w2, &w3, &w4, &w5;
-  __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
-    r = m == 0 ? w0 : m == 1 ? w1 : m == 2 ? w2 : m == 3 ? w3 : m == 4 ? w4 : w5;
-  }
-};
-
+// Stencil accessor over the LDS plane.
 template <int NV>
 struct LdsSrc {  // six cells of the LDS plane at base + m*stride
   double (*srec)[FP_N];
@@ -281,95 +75,6 @@ struct LdsSrc {  // six cells of the LDS plane at base + m*stride
     lds_get<NV>(srec, base + m * stride, r);
   }
 };
-
-// Nonlinear (WENO-L2IS) correction of one flagged face, field by field:
-// for each field k in `mask`, the left eigenvector row L^k is formed, the six
-// stencil cells are projected (Eq.(20)), split (Eq.(21)) and reconstructed
-// (Eq.(22)-(23)); the change with respect to the linear flux of that field is
-// back-projected (Eq.(24)).  Only one row and twelve split values are live.
-template <int NV, int DIR, int K, class Src>
-__device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, double al, double dvk,
-                                             double LFk, const KPhys& ph) {
-  double r[NV];
-  left_row<NV, DIR, K>(s, r);
-  double fp[6], fm[6];
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    LRec<NV> cm;
-    src.get(m, cm);
-    double F[NV], un;
-    lflux<NV, DIR>(cm, F, un);
-    const double vv = dot<NV>(r, cm.U);
-    const double gg = dot<NV>(r, F);
-    fp[m] = 0.5 * (gg + al * vv);
-    fm[m] = 0.5 * (gg - al * vv);
-  }
-  const double t = dvk * s.irho;
-  const double lam = ph.c_reg * (t * t);  // Eq.(32)
-  const double fw = weno_l2is(fp[0], fp[1], fp[2], fp[3], fp[4], lam, ph.eps_w) +
-                    weno_l2is(fm[5], fm[4], fm[3], fm[2], fm[1], lam, ph.eps_w);
-  return fw - (LFk + al * dvk);
-}
-
-template <int NV, int DIR, class Src>
-__device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, const KPhys& ph,
-                                                const unsigned long long* lfb, double (&dF)[NV]) {
-  double dU5[NV], Fc6[NV];
-  double am = 0.0, a0 = 0.0, ap = 0.0;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) dU5[i] = Fc6[i] = 0.0;
-  constexpr double cu[6] = {1.0, -5.0, 10.0, -10.0, 5.0, -1.0};
-  constexpr double cf[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    LRec<NV> cm;
-    src.get(m, cm);
-    double F[NV], un;
-    lflux<NV, DIR>(cm, F, un);
-    am = fmax(am, fabs(un - cm.c));
-    a0 = fmax(a0, fabs(un));
-    ap = fmax(ap, fabs(un + cm.c));
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      dU5[i] += cu[m] * cm.U[i];
-      Fc6[i] += cf[m] * F[i];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NV; ++i) Fc6[i] *= (1.0 / 60.0);
-  Roe<NV> s;
-  {
-    LRec<NV> c2, c3;
-    src.get(2, c2);
-    src.get(3, c3);
-    roe_light<NV, DIR>(c2, c3, ph, s);
-  }
-  double a[NV];
-  if (ph.split == SPLIT_LLF) {
-    a[0] = am;
-#pragma unroll
-    for (int k = 1; k < NV - 1; ++k) a[k] = a0;
-    a[NV - 1] = ap;
-  } else if (ph.split == SPLIT_ROE) {
-    a[0] = fabs(s.u[DIR] - s.c);
-#pragma unroll
-    for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
-    a[NV - 1] = fabs(s.u[DIR] + s.c);
-  } else {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] = __longlong_as_double((long long)lfb[k]);
-  }
-  double dv[NV], LF[NV], del[NV];
-  project<NV, DIR>(s, dU5, dv);
-  project<NV, DIR>(s, Fc6, LF);
-#define WL2_LF(K)                                                                          \
-  del[K] = ((mask >> K) & 1u)                                                              \
-               ? lean_field<NV, DIR, K>(src, s, a[K], dv[K] * (1.0 / 60.0), LF[K], ph)    \
-               : 0.0;
-  WL2_LF(0) WL2_LF(1) WL2_LF(2) WL2_LF(3) WL2_LF(4)
-#undef WL2_LF
-  back_project<NV, DIR>(s, del, dF);
-}
 
 // Column of cells at fixed (x, y): element offset of its (x, y) position
 // after the boundary mapping, and the momentum signs of mirror ghosts.
@@ -661,51 +366,16 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
-// Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
-// the face below the cell, side 1 the face above.  Returns the change of the
-// face flux (WENO minus linear, Eq.(33) per field).
-template <int NV, int DIR, int SPLIT, int HYB>
-__device__ __forceinline__ void face_delta(const double* U, const KGrid& g, const KPhys& ph,
-                                           const unsigned long long* lfb, int x, int y, int z,
-                                           int side, double (&dF)[NV]) {
-  struct Src {
-    const double* U;
-    const KGrid* g;
-    const KPhys* ph;
-    int c[3];
-    __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
-      double u[NV];
-      bool flip;
-      const int k = ghost_clamped(c[DIR] + m, g->n[DIR], g->bc_lo[DIR], g->bc_hi[DIR], flip);
-      int p[3] = {c[0], c[1], c[2]};
-      p[DIR] = k;
-      const long long off = p[0] + (long long)p[1] * g->stride[1] + (long long)p[2] * g->stride[2];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = U[v * g->ncell + off];
-      if (flip) u[1 + DIR] = -u[1 + DIR];
-      make_lrec<NV>(u, *ph, r);
-    }
-  } src{U, &g, &ph, {x, y, z}};
-  // face below the cell: stencil starts 3 cells below; face above: 2 below
-  src.c[DIR] += side ? -2 : -3;
-  double Flin[NV];
-  const unsigned mask =
-      face_linear_l<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin);
-  if (mask) {
-    lean_correction<NV, DIR>(src, mask, ph, lfb, dF);
-  } else {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) dF[v] = 0.0;
-  }
-}
-
-// One thread per listed cell: add the nonlinear part of the flux of its
-// flagged faces, in the fixed order x-, x+, y-, y+, z-, z+, to the output
-// (scaled by rk_b dt for a stage, 1 for dU/dt).  Each cell is owned by one
-// thread, so the result does not depend on scheduling.
+// Per listed cell: add the nonlinear part of the flux of its flagged faces,
+// summed in the fixed order x-, x+, y-, y+, z-, z+, to the output (scaled by
+// rk_b dt for a stage, 1 for dU/dt); eight lanes per cell (one per face) for
+// a short list, one lane per cell for a long one, with the same bits.  Each
+// cell is owned by one lane (group), so the result does not depend on
+// scheduling.  With a.cfl set, the CFL speed of the corrected cell is folded.
 template <int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
+  constexpr int GRP = 8;
   double scale = 1.0;
   if (OUT == OUT_RK) {
     const double dt = a.ctl->dt;
@@ -715,7 +385,11 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
   const unsigned int n = *a.list_n;
   double cfl_max = 0.0;
   bool cfl_bad = false;
-  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const unsigned int threads = gridDim.x * blockDim.x;
+  const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool grouped = n <= threads / GRP;  // short list: latency; long: a lane per cell
+  const unsigned int step = grouped ? threads / GRP : threads;
+  for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step) {
     const unsigned long long e = a.list[i];
     const long long off = (long long)(e >> 8);
     const unsigned cm = (unsigned)(e & 0xffu);
@@ -723,29 +397,19 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
     const int y = (int)((off / g.n[0]) % g.n[1]);
     const int z = (int)(off / g.stride[2]);
     double acc[NV];
+    if (grouped) grouped_correction<NV, GRP, SPLIT, HYB>(a.Uk, g, ph, a.ctl, x, y, z, cm, acc);
+    else serial_correction<NV, SPLIT, HYB>(a.Uk, g, ph, a.ctl, x, y, z, cm, acc);
+    if (!grouped || (threadIdx.x % GRP) == 0) {
+      double un[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int f = 0; f < 6; ++f) {
-      if (!((cm >> f) & 1u)) continue;
-      const int dir = f >> 1, side = f & 1;
-      double dF[NV];
-      if (dir == 0) face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, z, side, dF);
-      else if (dir == 1) face_delta<NV, 1, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, z, side, dF);
-      else face_delta<NV, 2, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[2], x, y, z, side, dF);
-      // dU = -(F_{+} - F_{-}) / dx: the face below adds, the face above subtracts
-      const double sg = side ? -1.0 : 1.0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += sg * dF[v];
-    }
-    double un[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      un[v] = a.out[v * g.ncell + off] + scale * (acc[v] * ph.inv_dx);
-      a.out[v * g.ncell + off] = un[v];
-    }
-    if (OUT == OUT_RK && a.cfl != nullptr) {
-      const double m[3] = {un[1], un[2], un[3]};
-      cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
+      for (int v = 0; v < NV; ++v) {
+        un[v] = a.out[v * g.ncell + off] + scale * (acc[v] * ph.inv_dx);
+        a.out[v * g.ncell + off] = un[v];
+      }
+      if (OUT == OUT_RK && a.cfl != nullptr) {
+        const double m[3] = {un[1], un[2], un[3]};
+        cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
+      }
     }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);

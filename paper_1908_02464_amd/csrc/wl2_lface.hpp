@@ -1,0 +1,425 @@
+// Face fluxes from "light" cell records (U, p, c, 1/sqrt(rho)): the linear
+// branch of one face, its nonlinear (WENO-L2IS) correction, and the helpers
+// they share.  Used by the fused 3D stage kernel and the 1D/2D row kernels;
+// stencil cells come through small accessor objects (`src.get(m, rec)`), so
+// the same arithmetic serves registers, LDS and global memory.
+#pragma once
+#include "wl2_device.hpp"
+
+namespace wl2 {
+
+// 1/x and 1/sqrt(x) from the hardware seeds refined by two Newton steps (the
+// seed error squares each step; the result is within a few ulp, not
+// correctly rounded).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+  }
+  return r;
+}
+
+__device__ __forceinline__ double fast_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
+template <int NV>
+struct LRec {
+  double U[NV];
+  double p, c, iw;  // pressure, sound speed, 1/sqrt(rho)
+};
+
+template <int NV>
+__device__ __forceinline__ void make_lrec(const double (&u)[NV], const KPhys& ph, LRec<NV>& r) {
+  constexpr int DIM = NV - 2;
+  const double iw = fast_rsqrt(u[0]);
+  const double ir = iw * iw;
+  double m2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
+  const double p = ph.gm1 * (u[NV - 1] - 0.5 * ir * m2);
+  const double c2 = ph.gamma * p * ir;
+  r.c = c2 * fast_rsqrt(c2);
+  r.p = p;
+  r.iw = iw;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) r.U[v] = u[v];
+}
+
+// Flux along DIR and normal velocity from a light record.
+template <int NV, int DIR>
+__device__ __forceinline__ void lflux(const LRec<NV>& r, double (&F)[NV], double& un) {
+  constexpr int DIM = NV - 2;
+  un = r.U[1 + DIR] * (r.iw * r.iw);
+  F[0] = r.U[1 + DIR];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) F[1 + k] = un * r.U[1 + k] + (k == DIR ? r.p : 0.0);
+  F[NV - 1] = (r.U[NV - 1] + r.p) * un;
+}
+
+template <int NV, int DIR>
+__device__ __forceinline__ void to_cellrec(const LRec<NV>& r, CellRec<NV>& c) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c.U[v] = r.U[v];
+  lflux<NV, DIR>(r, c.F, c.un);
+  c.c = r.c;
+  c.iw = r.iw;
+  c.p = r.p;
+}
+
+template <int NV, int DIR>
+__device__ __forceinline__ void roe_light(const LRec<NV>& L, const LRec<NV>& R, const KPhys& ph,
+                                          Roe<NV>& s) {
+  constexpr int DIM = NV - 2;
+  const double wl = L.U[0] * L.iw, wr = R.U[0] * R.iw;
+  const double is = fast_rcp(wl + wr);
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    s.u[k] = (L.U[1 + k] * L.iw + R.U[1 + k] * R.iw) * is;
+    q += s.u[k] * s.u[k];
+  }
+  s.q = 0.5 * q;
+  s.H = ((L.U[NV - 1] + L.p) * L.iw + (R.U[NV - 1] + R.p) * R.iw) * is;
+  const double c2 = ph.gm1 * (s.H - s.q);
+  s.ic = fast_rsqrt(c2);
+  s.c = c2 * s.ic;
+  s.b1 = ph.gm1 * s.ic * s.ic;
+  s.b2 = s.b1 * s.q;
+  s.irho = L.iw * R.iw;
+}
+
+// Linear-branch flux of one face from six light records; returns the mask
+// of fields whose detector asks for the nonlinear flux.
+// `src.get(m, rec)` supplies stencil cell m = 0..5 (j-2 .. j+3); cells are
+// requested in the pairs (0,5), (1,4), (2,3) so only two are live at a time.
+// SPLIT / HYB: compile-time splitting and switch modes, or -1 to read them
+// from ph at run time.
+template <int NV, int DIR, int SPLIT, int HYB, class Src>
+__device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& ph, double eps_thr,
+                                                  const unsigned long long* lfb, double (&Fh)[NV]) {
+  const int split = SPLIT >= 0 ? SPLIT : ph.split;
+  const int hybrid = HYB >= 0 ? HYB : ph.hybrid;
+  double dU5[NV], Fc6[NV];
+  double am, a0, ap;
+  LRec<NV> c2, c3;
+  {
+    LRec<NV> c0, c5;
+    src.get(0, c0);
+    src.get(5, c5);
+    double F0[NV], F5[NV], u0, u5;
+    lflux<NV, DIR>(c0, F0, u0);
+    lflux<NV, DIR>(c5, F5, u5);
+    am = fmax(fabs(u0 - c0.c), fabs(u5 - c5.c));
+    a0 = fmax(fabs(u0), fabs(u5));
+    ap = fmax(fabs(u0 + c0.c), fabs(u5 + c5.c));
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      dU5[i] = c0.U[i] - c5.U[i];
+      Fc6[i] = F0[i] + F5[i];
+    }
+  }
+  {
+    LRec<NV> c1, c4;
+    src.get(1, c1);
+    src.get(4, c4);
+    double F1[NV], F4[NV], u1, u4;
+    lflux<NV, DIR>(c1, F1, u1);
+    lflux<NV, DIR>(c4, F4, u4);
+    am = fmax(am, fmax(fabs(u1 - c1.c), fabs(u4 - c4.c)));
+    a0 = fmax(a0, fmax(fabs(u1), fabs(u4)));
+    ap = fmax(ap, fmax(fabs(u1 + c1.c), fabs(u4 + c4.c)));
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      dU5[i] += 5.0 * (c4.U[i] - c1.U[i]);
+      Fc6[i] -= 8.0 * (F1[i] + F4[i]);
+    }
+  }
+  src.get(2, c2);
+  src.get(3, c3);
+  {
+    double F2[NV], F3[NV], u2, u3;
+    lflux<NV, DIR>(c2, F2, u2);
+    lflux<NV, DIR>(c3, F3, u3);
+    am = fmax(am, fmax(fabs(u2 - c2.c), fabs(u3 - c3.c)));
+    a0 = fmax(a0, fmax(fabs(u2), fabs(u3)));
+    ap = fmax(ap, fmax(fabs(u2 + c2.c), fabs(u3 + c3.c)));
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      dU5[i] += 10.0 * (c2.U[i] - c3.U[i]);
+      Fc6[i] = (Fc6[i] + 37.0 * (F2[i] + F3[i])) * (1.0 / 60.0);
+    }
+  }
+  Roe<NV> s;
+  roe_light<NV, DIR>(c2, c3, ph, s);
+  double a[NV];
+  if (split == SPLIT_LLF) {
+    a[0] = am;
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a[k] = a0;
+    a[NV - 1] = ap;
+  } else if (split == SPLIT_ROE) {
+    a[0] = fabs(s.u[DIR] - s.c);
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
+    a[NV - 1] = fabs(s.u[DIR] + s.c);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] = __longlong_as_double((long long)lfb[k]);
+  }
+  double dv[NV], d[NV];
+  project<NV, DIR>(s, dU5, dv);
+  unsigned weno = 0;
+  double smax = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    dv[k] *= (1.0 / 60.0);
+    const double t = dv[k] * s.irho;
+    const double sig = t * t;  // Eq.(30)
+    smax = fmax(smax, sig);
+    if (!(sig < eps_thr)) weno |= 1u << k;
+    d[k] = a[k] * dv[k];
+  }
+  if (hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
+  else if (hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
+  else if (hybrid == HYB_LINEAR_ONLY) weno = 0u;
+  double Rd[NV];
+  back_project<NV, DIR>(s, d, Rd);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) Fh[i] = Fc6[i] + Rd[i];
+  return weno;
+}
+
+// Index of a line position clamped to [-3, n+2] and mapped through the
+// boundary rule; flip set for mirror ghosts.
+__device__ __forceinline__ int ghost_clamped(int k, int n, int lo, int hi, bool& flip) {
+  k = k < -3 ? -3 : (k > n + 2 ? n + 2 : k);
+  return ghost_index(k, n, lo, hi, flip);
+}
+
+// Stencil accessor over six records held in registers.
+template <int NV>
+struct WinSrc {  // the owner's z window (registers)
+  const LRec<NV>&w0, &w1, &w2, &w3, &w4, &w5;
+  __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
+    r = m == 0 ? w0 : m == 1 ? w1 : m == 2 ? w2 : m == 3 ? w3 : m == 4 ? w4 : w5;
+  }
+};
+
+// Nonlinear (WENO-L2IS) correction of one flagged face, field by field:
+// for each field k in `mask`, the left eigenvector row L^k is formed, the six
+// stencil cells are projected (Eq.(20)), split (Eq.(21)) and reconstructed
+// (Eq.(22)-(23)); the change with respect to the linear flux of that field is
+// back-projected (Eq.(24)).  Only one row and twelve split values are live.
+template <int NV, int DIR, int K, class Src>
+__device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, double al, double dvk,
+                                             double LFk, const KPhys& ph) {
+  double r[NV];
+  left_row<NV, DIR, K>(s, r);
+  double fp[6], fm[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    LRec<NV> cm;
+    src.get(m, cm);
+    double F[NV], un;
+    lflux<NV, DIR>(cm, F, un);
+    const double vv = dot<NV>(r, cm.U);
+    const double gg = dot<NV>(r, F);
+    fp[m] = 0.5 * (gg + al * vv);
+    fm[m] = 0.5 * (gg - al * vv);
+  }
+  const double t = dvk * s.irho;
+  const double lam = ph.c_reg * (t * t);  // Eq.(32)
+  const double fw = weno_l2is(fp[0], fp[1], fp[2], fp[3], fp[4], lam, ph.eps_w) +
+                    weno_l2is(fm[5], fm[4], fm[3], fm[2], fm[1], lam, ph.eps_w);
+  return fw - (LFk + al * dvk);
+}
+
+template <int NV, int DIR, class Src>
+__device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, const KPhys& ph,
+                                                const unsigned long long* lfb, double (&dF)[NV]) {
+  double dU5[NV], Fc6[NV];
+  double am = 0.0, a0 = 0.0, ap = 0.0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) dU5[i] = Fc6[i] = 0.0;
+  constexpr double cu[6] = {1.0, -5.0, 10.0, -10.0, 5.0, -1.0};
+  constexpr double cf[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    LRec<NV> cm;
+    src.get(m, cm);
+    double F[NV], un;
+    lflux<NV, DIR>(cm, F, un);
+    am = fmax(am, fabs(un - cm.c));
+    a0 = fmax(a0, fabs(un));
+    ap = fmax(ap, fabs(un + cm.c));
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      dU5[i] += cu[m] * cm.U[i];
+      Fc6[i] += cf[m] * F[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) Fc6[i] *= (1.0 / 60.0);
+  Roe<NV> s;
+  {
+    LRec<NV> c2, c3;
+    src.get(2, c2);
+    src.get(3, c3);
+    roe_light<NV, DIR>(c2, c3, ph, s);
+  }
+  double a[NV];
+  if (ph.split == SPLIT_LLF) {
+    a[0] = am;
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a[k] = a0;
+    a[NV - 1] = ap;
+  } else if (ph.split == SPLIT_ROE) {
+    a[0] = fabs(s.u[DIR] - s.c);
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
+    a[NV - 1] = fabs(s.u[DIR] + s.c);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a[k] = __longlong_as_double((long long)lfb[k]);
+  }
+  double dv[NV], LF[NV], del[NV];
+  project<NV, DIR>(s, dU5, dv);
+  project<NV, DIR>(s, Fc6, LF);
+#define WL2_LF(K)                                                                            \
+  if constexpr (K < NV) {                                                                    \
+    del[K] = ((mask >> K) & 1u)                                                              \
+                 ? lean_field<NV, DIR, K>(src, s, a[K], dv[K] * (1.0 / 60.0), LF[K], ph)    \
+                 : 0.0;                                                                      \
+  }
+  WL2_LF(0) WL2_LF(1) WL2_LF(2) WL2_LF(3) WL2_LF(4)
+#undef WL2_LF
+  back_project<NV, DIR>(s, del, dF);
+}
+
+// Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
+// the face below the cell, side 1 the face above.  Returns the change of the
+// face flux (WENO minus linear, Eq.(33) per field).
+template <int NV, int DIR, int SPLIT, int HYB>
+__device__ __forceinline__ void face_delta(const double* U, const KGrid& g, const KPhys& ph,
+                                           const unsigned long long* lfb, int x, int y, int z,
+                                           int side, double (&dF)[NV]) {
+  // the six stencil cells, loaded once (all loads issued before any use) and
+  // kept in registers for the linear flux and every field's correction; the
+  // face below the cell starts 3 cells below it, the face above 2 below
+  const int c0 = (DIR == 0 ? x : DIR == 1 ? y : z) + (side ? -2 : -3);
+  double u[6][NV];
+  bool flip[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const int k = ghost_clamped(c0 + m, g.n[DIR], g.bc_lo[DIR], g.bc_hi[DIR], flip[m]);
+    int p[3] = {x, y, z};
+    p[DIR] = k;
+    const long long off = p[0] + (long long)p[1] * g.stride[1] + (long long)p[2] * g.stride[2];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[m][v] = U[v * g.ncell + off];
+  }
+  LRec<NV> w[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    if (flip[m]) u[m][1 + DIR] = -u[m][1 + DIR];
+    make_lrec<NV>(u[m], ph, w[m]);
+  }
+  const WinSrc<NV> src{w[0], w[1], w[2], w[3], w[4], w[5]};
+  double Flin[NV];
+  const unsigned mask = face_linear_l<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin);
+  if (mask) {
+    lean_correction<NV, DIR>(src, mask, ph, lfb, dF);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+  }
+}
+
+// Nonlinear correction of one listed cell by one lane: the flagged faces in
+// the fixed order x-, x+, y-, y+, z-, z+, +dF for the face below the cell and
+// -dF for the face above.
+template <int NV, int SPLIT, int HYB>
+__device__ __forceinline__ void serial_correction(const double* U, const KGrid& g,
+                                                  const KPhys& ph, const StepCtl* ctl, int x,
+                                                  int y, int z, unsigned cm, double (&acc)[NV]) {
+  constexpr int NF = 2 * (NV - 2);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int f = 0; f < NF; ++f) {
+    if (!((cm >> f) & 1u)) continue;
+    const int dir = f >> 1, side = f & 1;
+    double dF[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+    if (dir == 0) {
+      face_delta<NV, 0, SPLIT, HYB>(U, g, ph, ctl->lf_bits[0], x, y, z, side, dF);
+    } else if (dir == 1) {
+      if constexpr (NV >= 4)
+        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[1], x, y, z, side, dF);
+    } else {
+      if constexpr (NV >= 5)
+        face_delta<NV, (NV >= 5 ? 2 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[2], x, y, z, side, dF);
+    }
+    const double sg = side ? -1.0 : 1.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += sg * dF[v];
+  }
+}
+
+// Nonlinear correction of one listed cell, computed by a group of GRP lanes
+// of one wavefront: lane f of the group takes face f = 2 dir + side (x-, x+,
+// y-, y+, z-, z+) if the mask flags it, and every lane of the group gets the
+// sum of +-dF over the flagged faces in that fixed order (the face below the
+// cell adds, the face above subtracts): the same bits as serial_correction,
+// with one face of latency instead of six (for short lists; a long list
+// keeps every lane busy with one cell each).
+template <int NV, int GRP, int SPLIT, int HYB>
+__device__ __forceinline__ void grouped_correction(const double* U, const KGrid& g,
+                                                   const KPhys& ph, const StepCtl* ctl, int x,
+                                                   int y, int z, unsigned cm, double (&acc)[NV]) {
+  constexpr int NF = 2 * (NV - 2);
+  static_assert(NF <= GRP && (64 % GRP) == 0, "one lane per face, groups inside a wavefront");
+  const int lane = threadIdx.x & 63;
+  const int f = lane % GRP;
+  const int lane0 = lane - f;
+  double dF[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+  if (f < NF && ((cm >> f) & 1u)) {
+    const int dir = f >> 1, side = f & 1;
+    if (dir == 0) {
+      face_delta<NV, 0, SPLIT, HYB>(U, g, ph, ctl->lf_bits[0], x, y, z, side, dF);
+    } else if (dir == 1) {
+      if constexpr (NV >= 4)
+        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[1], x, y, z, side, dF);
+    } else {
+      if constexpr (NV >= 5)
+        face_delta<NV, (NV >= 5 ? 2 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[2], x, y, z, side, dF);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int ff = 0; ff < NF; ++ff) {
+    double d[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = __shfl(dF[v], lane0 + ff, 64);
+    if ((cm >> ff) & 1u) {
+      const double sg = (ff & 1) ? -1.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sg * d[v];
+    }
+  }
+}
+
+}  // namespace wl2

@@ -1,0 +1,69 @@
+// Dispatch of the fused 1D/2D row kernels (wl2_row.hpp).
+#include <hip/hip_runtime.h>
+
+#include "wl2_row.hpp"
+#include "wl2_row_launch.hpp"
+
+namespace wl2 {
+
+static_assert(ROW_TILE == RT, "one tile width for host and device");
+
+namespace {
+
+template <int NV, int OUT>
+void launch_nv(const RowLaunch& L, const RowArgs& a, dim3 grid, int ych, int tiles_x) {
+  if (L.fast)
+    hipLaunchKernelGGL((row_kernel<NV, OUT, 0, 0>), grid, dim3(RW), 0, L.stream, a, L.g, L.ph, ych, tiles_x);
+  else
+    hipLaunchKernelGGL((row_kernel<NV, OUT, -1, -1>), grid, dim3(RW), 0, L.stream, a, L.g, L.ph, ych, tiles_x);
+}
+
+}  // namespace
+
+hipError_t row_reset(const RowLaunch& L) {
+  hipLaunchKernelGGL(row_list_reset_kernel, dim3(1), dim3(64), 0, L.stream, L.list_n);
+  return hipGetLastError();
+}
+
+hipError_t row_fix(const RowLaunch& L) {
+  const RowArgs a{L.Uk, L.out, L.Un, L.ctl, L.rk_a, L.rk_b, L.list, L.list_n, 0ull};
+  const dim3 fg(1024), fb(128);
+#define WL2_FIX(NV, O)                                                                     \
+  do {                                                                                     \
+    if (L.fast)                                                                            \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, 0, 0>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+    else                                                                                   \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, -1, -1>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+  } while (0)
+  if (L.nvar == 3) {
+    if (L.out_kind == OUT_RK) WL2_FIX(3, OUT_RK); else WL2_FIX(3, OUT_WRITE);
+  } else if (L.nvar == 4) {
+    if (L.out_kind == OUT_RK) WL2_FIX(4, OUT_RK); else WL2_FIX(4, OUT_WRITE);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef WL2_FIX
+  return hipGetLastError();
+}
+
+hipError_t row_launch(const RowLaunch& L) {
+  const RowArgs a{L.Uk, L.out, L.Un, L.ctl, L.rk_a, L.rk_b, L.list, L.list_n, 0ull};
+  const int tiles_x = (L.g.n[0] + RT - 1) / RT;
+  const int ych = L.nvar == 3 ? 1 : (L.ych < 1 ? 1 : (L.ych > ROW_MAX_YCH ? ROW_MAX_YCH : L.ych));
+  const long long chunks = L.nvar == 3 ? 1 : (L.g.n[1] + ych - 1) / ych;
+  const long long items = (long long)tiles_x * chunks;
+  if (items < 1 || items > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)items);
+  if (L.nvar == 3) {
+    if (L.out_kind == OUT_RK) launch_nv<3, OUT_RK>(L, a, grid, ych, tiles_x);
+    else launch_nv<3, OUT_WRITE>(L, a, grid, ych, tiles_x);
+  } else if (L.nvar == 4) {
+    if (L.out_kind == OUT_RK) launch_nv<4, OUT_RK>(L, a, grid, ych, tiles_x);
+    else launch_nv<4, OUT_WRITE>(L, a, grid, ych, tiles_x);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace wl2

@@ -1,0 +1,378 @@
+// Fused 1D/2D stage kernel (gfx950, FP64): both sweep directions, the flux
+// difference of Eq.(19) and the SSP-RK3 stage combination in one pass over
+// HBM, for one grid (row_kernel) or for many grids (the batched form).
+//
+// Work item: one wavefront owns RT = 63 consecutive columns of one grid and
+// marches along y through a chunk of rows (1D: the single row).  Each lane
+// keeps a six-cell window of light records (U, p, c, 1/sqrt(rho)) of its
+// column, four in registers and the two oldest in an LDS ring, so the y face
+// of every row is formed without another load.  The current row plus a
+// three-cell x halo is staged in LDS; lane t computes the x face on the left
+// of column t (64 faces for 63 cells) and the right face of a cell arrives
+// from the next lane by a cross-lane shuffle, so every face flux is computed
+// once and both neighbours use the same bits.  Faces whose detector asks for
+// the nonlinear flux are only flagged in the march: their cells go to a
+// correction list and a separate kernel adds the WENO-L2IS part (one thread
+// per listed cell, so a discontinuity does not serialise the item that holds
+// it).  Rows are read with coalesced loads; the next row of the window and of
+// the halo is prefetched a row ahead, with the sign flip of mirror ghosts
+// applied at use.
+#pragma once
+#include "wl2_lface.hpp"
+
+namespace wl2 {
+
+constexpr int RW = 64;      // lanes of a work item (one wavefront)
+constexpr int RT = RW - 1;  // columns owned by an item: RW x faces
+constexpr int RB = RW + 5;  // row buffer: cells x0-3 .. x0+RW+1
+
+struct RowArgs {
+  const double* Uk;    // stage input
+  double* out;         // RK: U^(k+1); WRITE: dU/dt
+  const double* Un;    // RK: U^n (read when rk_a != 0)
+  const StepCtl* ctl;  // dt and the global LF speeds
+  double rk_a, rk_b;   // RK: out = rk_a U^n + rk_b (Uk + dt dU)
+  unsigned long long* list;  // cells next to a face that needs the WENO flux
+  unsigned int* list_n;      // entries in list
+  unsigned long long tag;    // or-ed into every entry (the batch slot << 40)
+};
+
+// Entry of the correction list: tag | element offset << 8 | face mask (bit 0
+// x-, 1 x+, 2 y-, 3 y+).  Appended with one atomic per wavefront.
+__device__ __forceinline__ void list_append(const RowArgs& a, long long off, unsigned cm) {
+  const unsigned long long ball = __ballot(cm != 0u);
+  if (!ball) return;
+  const int lane = threadIdx.x & (RW - 1);
+  const int leader = __ffsll((long long)ball) - 1;
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(a.list_n, (unsigned int)__popcll(ball));
+  base = __shfl(base, leader, RW);
+  if (cm) {
+    const unsigned int rank = __popcll(ball & ((1ull << lane) - 1ull));
+    a.list[base + rank] = a.tag | ((unsigned long long)off << 8) | cm;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void row_put(double (*buf)[RB], int i, const LRec<NV>& r) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) buf[v][i] = r.U[v];
+  buf[NV][i] = r.p;
+  buf[NV + 1][i] = r.c;
+  buf[NV + 2][i] = r.iw;
+}
+
+template <int NV>
+struct RowSrc {  // six cells of the row buffer from `base`
+  double (*buf)[RB];
+  int base;
+  __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
+    const int i = base + m;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.U[v] = buf[v][i];
+    r.p = buf[NV][i];
+    r.c = buf[NV + 1][i];
+    r.iw = buf[NV + 2][i];
+  }
+};
+
+// Per-lane ring of the two oldest cells of the y window: [2][NV+3][RW].
+template <int NV>
+__device__ __forceinline__ void ring_put(double (*ring)[NV + 3][RW], int slot, int lane,
+                                         const LRec<NV>& r) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ring[slot][v][lane] = r.U[v];
+  ring[slot][NV][lane] = r.p;
+  ring[slot][NV + 1][lane] = r.c;
+  ring[slot][NV + 2][lane] = r.iw;
+}
+
+template <int NV>
+struct RingSrc {  // y stencil: cells j-2, j-1 from the ring, j .. j+3 registers
+  double (*ring)[NV + 3][RW];
+  int slot0, slot1, lane;
+  const LRec<NV>&r0, &r1, &r2, &r3;
+  __device__ __forceinline__ void ring_get(int slot, LRec<NV>& r) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.U[v] = ring[slot][v][lane];
+    r.p = ring[slot][NV][lane];
+    r.c = ring[slot][NV + 1][lane];
+    r.iw = ring[slot][NV + 2][lane];
+  }
+  __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
+    if (m == 0) ring_get(slot0, r);
+    else if (m == 1) ring_get(slot1, r);
+    else r = m == 2 ? r0 : m == 3 ? r1 : m == 4 ? r2 : r3;
+  }
+};
+
+template <int NV>
+struct Win6Src {  // six records in registers
+  const LRec<NV> (&w)[6];
+  __device__ __forceinline__ void get(int m, LRec<NV>& r) const { r = w[m]; }
+};
+
+// Raw cell (column element offset xy, row y) of a 2D grid, ghost-mapped in
+// y; the mirror flip of the y momentum is reported, not applied.
+template <int NV>
+__device__ __forceinline__ void row_load_raw(const double* __restrict__ U, const KGrid& g,
+                                             long long xy, int y, double (&u)[NV]) {
+  bool fy = false;
+  const int iy = (y >= 0 && y < g.n[1]) ? y : ghost_clamped(y, g.n[1], g.bc_lo[1], g.bc_hi[1], fy);
+  const long long off = xy + (long long)iy * g.stride[1];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
+}
+
+template <int NV>
+__device__ __forceinline__ void row_flip(const KGrid& g, bool fx, int y, double (&u)[NV]) {
+  bool fy = false;
+  if (NV >= 4 && (y < 0 || y >= g.n[1])) (void)ghost_clamped(y, g.n[1], g.bc_lo[1], g.bc_hi[1], fy);
+  if (fx) u[1] = -u[1];
+  if (NV >= 4 && fy) u[2] = -u[2];
+}
+
+// One work item: columns x0 .. x0+RT-1 (clipped to the grid), rows y0 .. y1-1
+// (1D: y0 = 0, y1 = 1): the linear-branch fluxes of all its faces, Eq.(19)
+// and the stage combination; cells next to a flagged face are listed.
+// Called by whole wavefronts; `buf` is the item's LDS row buffer [NV+3][RB],
+// `ring` its window ring [2][NV+3][RW] (2D).
+template <int NV, int OUT, int SPLIT, int HYB>
+__device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const KPhys& ph,
+                                         double (*buf)[RB], double (*ring)[NV + 3][RW], int x0,
+                                         int y0, int y1, double dt) {
+  const int lane = threadIdx.x & (RW - 1);
+  const unsigned long long* lfx = a.ctl->lf_bits[0];
+  const unsigned long long* lfy = a.ctl->lf_bits[1];
+  // the lane's column (a ghost or the next item's column for lane RT and past
+  // the grid edge: those fill the row buffer but own no cell)
+  bool fx;
+  const int cx = ghost_clamped(x0 + lane, g.n[0], g.bc_lo[0], g.bc_hi[0], fx);
+  const bool own = lane < RT && x0 + lane < g.n[0];
+  // halo cells: lanes 0-2 fill slots 0-2 (x0-3 .. x0-1), lanes 3-4 slots
+  // RW+3, RW+4 (x0+RW, x0+RW+1)
+  const bool halo = lane < 5;
+  const int hslot = lane < 3 ? lane : RW + lane;
+  bool fxh = false;
+  const int hx = halo ? ghost_clamped(x0 - 3 + hslot, g.n[0], g.bc_lo[0], g.bc_hi[0], fxh) : 0;
+  const long long oxy = cx;  // row 0 element offset of the column (x stride 1)
+  const long long hxy = hx;
+
+  if constexpr (NV == 3) {
+    // 1D: one row
+    double u[NV];
+    row_load_raw<NV>(a.Uk, g, oxy, 0, u);
+    row_flip<NV>(g, fx, 0, u);
+    LRec<NV> own_rec;
+    make_lrec<NV>(u, ph, own_rec);
+    row_put<NV>(buf, lane + 3, own_rec);
+    if (halo) {
+      double hu[NV];
+      row_load_raw<NV>(a.Uk, g, hxy, 0, hu);
+      row_flip<NV>(g, fxh, 0, hu);
+      LRec<NV> hr;
+      make_lrec<NV>(hu, ph, hr);
+      row_put<NV>(buf, hslot, hr);
+    }
+    double unp[NV] = {};
+    if (OUT == OUT_RK && a.rk_a != 0.0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) unp[v] = __builtin_nontemporal_load(&a.Un[v * g.ncell + oxy]);
+    }
+    __syncthreads();
+    double Fx[NV];
+    const unsigned mx =
+        face_linear_l<NV, 0, SPLIT, HYB>(RowSrc<NV>{buf, lane}, ph, ph.eps_thr[0], lfx, Fx);
+    double Fr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fr[v] = __shfl_down(Fx[v], 1, RW);
+    const unsigned mxr = __shfl_down(mx, 1, RW);
+    list_append(a, oxy, own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u)) : 0u);
+    if (own) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double dU = (Fx[v] - Fr[v]) * ph.inv_dx;
+        if (OUT == OUT_RK) {
+          double r = a.rk_b * (own_rec.U[v] + dt * dU);
+          if (a.rk_a != 0.0) r += a.rk_a * unp[v];
+          __builtin_nontemporal_store(r, &a.out[v * g.ncell + oxy]);
+        } else {
+          __builtin_nontemporal_store(dU, &a.out[v * g.ncell + oxy]);
+        }
+      }
+    }
+    __syncthreads();  // the buffer is reused by the next item
+  } else {
+    // 2D: column window = cells y-2, y-1 (LDS ring, slot = row & 1) and
+    // y .. y+3 (registers r0..r3) at the top of row y
+    LRec<NV> r0, r1, r2, r3;
+    double Fyp[NV];
+    double upre[NV], hpre[NV];
+    bool yprev;  // face y - 1/2 needs the nonlinear flux
+    {
+      LRec<NV> cm3, cm2, cm1;
+      double u[NV];
+      row_load_raw<NV>(a.Uk, g, oxy, y0 - 3, u);
+      row_flip<NV>(g, fx, y0 - 3, u);
+      make_lrec<NV>(u, ph, cm3);
+      row_load_raw<NV>(a.Uk, g, oxy, y0 - 2, u);
+      row_flip<NV>(g, fx, y0 - 2, u);
+      make_lrec<NV>(u, ph, cm2);
+      row_load_raw<NV>(a.Uk, g, oxy, y0 - 1, u);
+      row_flip<NV>(g, fx, y0 - 1, u);
+      make_lrec<NV>(u, ph, cm1);
+      row_load_raw<NV>(a.Uk, g, oxy, y0, u);
+      row_flip<NV>(g, fx, y0, u);
+      make_lrec<NV>(u, ph, r0);
+      row_load_raw<NV>(a.Uk, g, oxy, y0 + 1, u);
+      row_flip<NV>(g, fx, y0 + 1, u);
+      make_lrec<NV>(u, ph, r1);
+      row_load_raw<NV>(a.Uk, g, oxy, y0 + 2, u);
+      row_flip<NV>(g, fx, y0 + 2, u);
+      make_lrec<NV>(u, ph, r2);
+      row_load_raw<NV>(a.Uk, g, oxy, y0 + 3, u);
+      row_flip<NV>(g, fx, y0 + 3, u);
+      make_lrec<NV>(u, ph, r3);
+      ring_put<NV>(ring, (y0 - 2) & 1, lane, cm2);
+      ring_put<NV>(ring, (y0 - 1) & 1, lane, cm1);
+      // face y0 - 1/2: cells y0-3 .. y0+2
+      const LRec<NV> wp[6] = {cm3, cm2, cm1, r0, r1, r2};
+      yprev = face_linear_l<NV, 1, SPLIT, HYB>(Win6Src<NV>{wp}, ph, ph.eps_thr[1], lfy, Fyp) != 0u;
+      row_load_raw<NV>(a.Uk, g, oxy, y0 + 4, upre);
+      if (halo) row_load_raw<NV>(a.Uk, g, hxy, y0, hpre);
+    }
+    for (int y = y0; y < y1; ++y) {
+      row_put<NV>(buf, lane + 3, r0);  // cell (x, y)
+      if (halo) {
+        row_flip<NV>(g, fxh, y, hpre);
+        LRec<NV> hr;
+        make_lrec<NV>(hpre, ph, hr);
+        row_put<NV>(buf, hslot, hr);
+        asm volatile("" ::: "memory");  // the prefetch below stays after this use
+        row_load_raw<NV>(a.Uk, g, hxy, y + 1, hpre);
+      }
+      __syncthreads();
+      // x face on the left of column x0+lane (cells x-3 .. x+2 = slots lane .. lane+5)
+      double Fx[NV];
+      const unsigned mx =
+          face_linear_l<NV, 0, SPLIT, HYB>(RowSrc<NV>{buf, lane}, ph, ph.eps_thr[0], lfx, Fx);
+      const long long off = oxy + (long long)y * g.stride[1];
+      double unp[NV] = {};
+      if (OUT == OUT_RK && a.rk_a != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) unp[v] = __builtin_nontemporal_load(&a.Un[v * g.ncell + off]);
+      }
+      // y face y + 1/2: cells y-2, y-1 (ring), y .. y+3 (registers)
+      double Fy[NV];
+      const bool ycur = face_linear_l<NV, 1, SPLIT, HYB>(
+                            RingSrc<NV>{ring, (y - 2) & 1, (y - 1) & 1, lane, r0, r1, r2, r3}, ph,
+                            ph.eps_thr[1], lfy, Fy) != 0u;
+      double Fr[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fr[v] = __shfl_down(Fx[v], 1, RW);
+      const unsigned mxr = __shfl_down(mx, 1, RW);
+      list_append(a, off,
+                  own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u) | (yprev ? 4u : 0u) | (ycur ? 8u : 0u)) : 0u);
+      yprev = ycur;
+      if (own) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double dU = ((Fx[v] - Fr[v]) + (Fyp[v] - Fy[v])) * ph.inv_dx;
+          if (OUT == OUT_RK) {
+            double r = a.rk_b * (r0.U[v] + dt * dU);
+            if (a.rk_a != 0.0) r += a.rk_a * unp[v];
+            __builtin_nontemporal_store(r, &a.out[v * g.ncell + off]);
+          } else {
+            __builtin_nontemporal_store(dU, &a.out[v * g.ncell + off]);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fyp[v] = Fy[v];
+      // retire cell y into the ring (over cell y-2), shift, make cell y+4
+      // from the prefetch and prefetch y+5 into the freed registers
+      ring_put<NV>(ring, y & 1, lane, r0);
+      r0 = r1;
+      r1 = r2;
+      r2 = r3;
+      row_flip<NV>(g, fx, y + 4, upre);
+      make_lrec<NV>(upre, ph, r3);
+      asm volatile("" ::"v"(r3.U[0]), "v"(r3.U[NV - 1]), "v"(r3.p), "v"(r3.c), "v"(r3.iw)
+                   : "memory");
+      row_load_raw<NV>(a.Uk, g, oxy, y + 5, upre);
+      __syncthreads();  // row buffer free for the next row
+    }
+  }
+}
+
+// Lanes per listed cell in the correction kernels for short lists (one per
+// face).
+constexpr int FIX_GRP = 4;
+
+// Nonlinear part of the flux of the flagged faces of one listed cell at
+// element offset `off` (face order x-, x+, y-, y+, as in the 3D correction
+// kernel), added to the output; `scale` = rk_b dt for a stage, 1 for dU/dt.
+// grouped: FIX_GRP lanes share the cell (one face each) and the group's first
+// lane writes; else one lane does all.  Each face is recomputed from the
+// stage input by both of its cells with the same operations, so both get
+// the same bits.
+template <int NV, int SPLIT, int HYB>
+__device__ __forceinline__ void row_fix_cell(const double* Uk, double* out, const StepCtl* ctl,
+                                             const KGrid& g, const KPhys& ph, long long off,
+                                             unsigned cm, double scale, bool grouped) {
+  const int x = (int)(off % g.n[0]);
+  const int y = (int)(off / g.n[0]);
+  double acc[NV];
+  if (grouped) grouped_correction<NV, FIX_GRP, SPLIT, HYB>(Uk, g, ph, ctl, x, y, 0, cm, acc);
+  else serial_correction<NV, SPLIT, HYB>(Uk, g, ph, ctl, x, y, 0, cm, acc);
+  if (!grouped || (threadIdx.x % FIX_GRP) == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v * g.ncell + off] += scale * (acc[v] * ph.inv_dx);
+  }
+}
+
+// Single grid.  A list that gives every group at most one cell is taken
+// FIX_GRP lanes per cell (latency), a longer one a lane per cell (throughput).
+template <int NV, int OUT, int SPLIT, int HYB>
+__global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys ph) {
+  double scale = 1.0;
+  if (OUT == OUT_RK) {
+    const double dt = a.ctl->dt;
+    if (!(dt > 0.0)) return;
+    scale = a.rk_b * dt;
+  }
+  const unsigned int n = *a.list_n;
+  const unsigned int threads = gridDim.x * blockDim.x;
+  const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool grouped = n <= threads / FIX_GRP;
+  const unsigned int step = grouped ? threads / FIX_GRP : threads;
+  for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
+    const unsigned long long e = a.list[i];
+    row_fix_cell<NV, SPLIT, HYB>(a.Uk, a.out, a.ctl, g, ph, (long long)((e >> 8) & 0xffffffffull),
+                                 (unsigned)(e & 0xffu), scale, grouped);
+  }
+}
+
+[[maybe_unused]] static __global__ void row_list_reset_kernel(unsigned int* n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *n = 0u;
+}
+
+// Single grid: item = (x tile, chunk of `ych` rows), one wavefront each.
+template <int NV, int OUT, int SPLIT, int HYB>
+__global__ __launch_bounds__(RW, 2) void row_kernel(RowArgs a, KGrid g, KPhys ph, int ych,
+                                                    int tiles_x) {
+  __shared__ double buf[NV + 3][RB];
+  __shared__ double ring[2][NV + 3][RW];
+  double dt = 0.0;
+  if (OUT == OUT_RK) {
+    dt = a.ctl->dt;
+    if (!(dt > 0.0)) return;  // finished run: leave the state untouched
+  }
+  const int item = blockIdx.x;
+  const int tx = item % tiles_x, ty = item / tiles_x;
+  const int y0 = ty * ych;
+  const int y1 = min(y0 + ych, g.n[1]);
+  row_item<NV, OUT, SPLIT, HYB>(a, g, ph, buf, ring, tx * RT, y0, y1, dt);
+}
+
+}  // namespace wl2

@@ -59,7 +59,7 @@ def run_batched(requests, budget_bytes: int, max_slots: int = 1024, continuous: 
                 steps_per_poll: int = 4, keep_results: bool = True, shape=None):
     """Batched execution; continuous=True honours arrival times (serving),
     False admits everything as soon as memory allows (closed batch).
-    shape = (seg, blocks) of the batched sweeps (e.g. from the autotuner)."""
+    shape = (rows, blocks) of the batched kernels (e.g. from the autotuner)."""
     eng = capi.Batch(budget_bytes, max_slots)
     if shape:
         eng.tune(*shape)
@@ -153,9 +153,9 @@ def serve_stream(n_req=1024, rate=200.0, seed=0, budget_gib=4.0, steps=(50, 2000
     budget = int(budget_gib * (1 << 30))
     shape = None
     if autotune:
-        seg, blocks, times = tuner.tune_batch(reqs, budget, steps=4, max_runs=256)
-        shape = (seg, blocks)
-        log(f"[serve] autotuned batched sweeps: seg={seg} blocks={blocks} "
+        rows, blocks, times = tuner.tune_batch(reqs, budget, steps=4, max_runs=256)
+        shape = (rows, blocks)
+        log(f"[serve] autotuned batched kernels: rows={rows} blocks={blocks} "
             f"({times[shape]:.3f} ms/step on {min(256, n_req)} runs)")
     out = {"metric": "served time-to-solution p50/p99 and Mcell-updates/s per RK stage",
            "unit": "s; Mcell-updates/s", "data": "synthetic", "dtype": "f64",
@@ -163,7 +163,7 @@ def serve_stream(n_req=1024, rate=200.0, seed=0, budget_gib=4.0, steps=(50, 2000
                                   f"N in [128,8192], 30% 2D side in [64,512], "
                                   f"{steps[0]}-{steps[1]} steps",
                       "budget_bytes": budget, "seed": seed,
-                      "batched_shape": {"seg": shape[0], "blocks": shape[1]} if shape else None}}
+                      "batched_shape": {"rows": shape[0], "blocks": shape[1]} if shape else None}}
     results = {}
     for mode in modes:
         torch.cuda.synchronize()

@@ -226,16 +226,16 @@ def test_serving_equals_alone(capi):
 
 
 def test_batch_results_independent_of_launch_shape(capi):
-    """Pencil length and persistent grid size change no bit of any run."""
+    """Rows per work item and persistent grid size change no bit of any run."""
     items = _mix()
     ref = _run_batch(capi, items)
     for shape in [(4, 512), (16, 8192), (8, 64)]:
-        say(f"[batch] seg={shape[0]} blocks={shape[1]}")
+        say(f"[batch] rows={shape[0]} blocks={shape[1]}")
         got = _run_batch(capi, items, shape=shape)
         for name, *_ in items:
             assert np.array_equal(got[name][0], ref[name][0]), (name, shape)
     eng = capi.Batch(MiB, 4)
-    for bad in [(3, 0), (32, 0), (0, 63), (0, 65537)]:
+    for bad in [(-1, 0), (63, 0), (0, 63), (0, 65537)]:
         with pytest.raises(capi.WenoL2ISError):
             eng.tune(*bad)
     eng.close()
@@ -251,7 +251,7 @@ def test_batch_tune_mid_run(capi):
         nx, ny, nz = _shape(U)
         slots[eng.admit(U, nx, ny, nz, dx, te)] = name
     res, k = {}, 0
-    shapes = [(4, 1024), (16, 2048), (8, 4096)]
+    shapes = [(4, 1024), (16, 2048), (1, 4096)]
     while len(res) < len(items):
         eng.tune(*shapes[k % 3])
         k += 1
@@ -267,9 +267,9 @@ def test_batch_tune_mid_run(capi):
 def test_autotuner_batch(capi):
     from paper_1908_02464_amd import autotune
     reqs = w.request_stream(n_req=16, rate=1000.0, seed=9, n1d=(64, 2000), n2d=(16, 128))
-    seg, blocks, times = autotune.tune_batch(reqs, 64 * MiB, steps=2, segs=(4, 8),
-                                             blocks=(512, 2048), verbose=True)
-    assert (seg, blocks) in times and len(times) == 4
+    rows, blocks, times = autotune.tune_batch(reqs, 64 * MiB, steps=2, rows=(4, 8),
+                                              blocks=(512, 2048), verbose=True)
+    assert (rows, blocks) in times and len(times) == 4
     assert all(t > 0 for t in times.values())
 
 
