@@ -95,7 +95,7 @@ __global__ __launch_bounds__(128) void batch_fix_kernel(const BGrid* __restrict_
   const unsigned int n = *list_n;
   const unsigned int threads = gridDim.x * blockDim.x;
   const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool grouped = n <= threads / FIX_GRP;
+  const bool grouped = (unsigned long long)n * FIX_GRP <= FIX_GROUPED_LANES && n <= threads / FIX_GRP;
   const unsigned int step = grouped ? threads / FIX_GRP : threads;
   for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
     const unsigned long long e = list[i];

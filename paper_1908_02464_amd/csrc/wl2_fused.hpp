@@ -387,7 +387,7 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
   bool cfl_bad = false;
   const unsigned int threads = gridDim.x * blockDim.x;
   const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool grouped = n <= threads / GRP;  // short list: latency; long: a lane per cell
+  const bool grouped = (unsigned long long)n * GRP <= FIX_GROUPED_LANES && n <= threads / GRP;
   const unsigned int step = grouped ? threads / GRP : threads;
   for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step) {
     const unsigned long long e = a.list[i];

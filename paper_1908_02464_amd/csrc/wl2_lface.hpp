@@ -376,6 +376,13 @@ __device__ __forceinline__ void serial_correction(const double* U, const KGrid& 
   }
 }
 
+// Lanes given to a correction list in the one-lane-per-face mode: at most
+// one wavefront per SIMD of the chip.  Lanes of one wavefront that take
+// faces of different directions run one after the other, so per cell the
+// grouped mode costs more lane-time than one lane per cell; it pays only
+// while the list leaves the chip mostly idle.
+constexpr unsigned long long FIX_GROUPED_LANES = 64ull * 1024ull;
+
 // Nonlinear correction of one listed cell, computed by a group of GRP lanes
 // of one wavefront: lane f of the group takes face f = 2 dir + side (x-, x+,
 // y-, y+, z-, z+) if the mask flags it, and every lane of the group gets the
