@@ -72,6 +72,51 @@ def cpu_baseline(U0, dx, min_seconds=10.0):
                       f"256^3 initial field ({el:.1f} s, single thread)"}
 
 
+def other_configs(torch, capi, workloads):
+    """The 1D and 2D workloads run to their end: Sod 200 to t = 0.2,
+    Shu-Osher 1600 to t = 1.8 (transmissive), 2D four-quadrant 1024^2 for 200
+    steps.  Each through weno_l2is_advance on the fused 1D/2D kernel, timed
+    with events on the library's stream after one untimed warm-up run."""
+    out = {}
+    cases = []
+    U, dx = workloads.sod(200)
+    cases.append(("sod200_t0.2", U, dx, (200, 1, 1), 0.2, None))
+    U, dx = workloads.shu_osher(1600)
+    cases.append(("shu_osher1600_t1.8", U, dx, (1600, 1, 1), 1.8, None))
+    U, dx, _ = workloads.four_quadrant_2d(1024, 1024, 2024)
+    cases.append(("quad2d_1024x1024_200steps", U, dx, (1024, 1024, 1), 1e300, 200))
+    for name, U0, dx, shape, t_end, nsteps in cases:
+        ctx = capi.Context(*shape, dx, GAMMA)
+        ncell = shape[0] * shape[1] * shape[2]
+        res = None
+        for rep in range(2):  # warm-up run, then the timed one
+            Ud = torch.from_numpy(U0).cuda()
+            ctx.set_time(0.0)
+            t0c = ctx.clock()[2]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            if nsteps:
+                ctx.advance(Ud, nsteps, t_end)
+            else:
+                while True:
+                    ctx.advance(Ud, 256, t_end)
+                    if not ctx.time()[0] < t_end:
+                        break
+            e1.record(ctx.stream)
+            e1.synchronize()
+            t, _, steps = ctx.clock()
+            steps -= t0c
+            ms = e0.elapsed_time(e1)
+            res = {"steps": int(steps), "t": t if t_end < 1e299 else None, "ms_total": round(ms, 3),
+                   "ms_per_step": round(ms / steps, 5),
+                   "Mcell_updates_per_s_per_stage": round(ncell * 3 * steps / (ms * 1e-3) / 1e6, 2),
+                   "status": ctx.status()}
+        out[name] = res
+        log(f"[bench]   {name}: {res}")
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +129,8 @@ def main():
     ap.add_argument("--wpe", type=int, default=0, help="fused kernel waves per SIMD (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1D / 2D single-grid workloads")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the batched-serving leg (Poisson stream of 1D/2D Riemann runs)")
     ap.add_argument("--serve-requests", type=int, default=1024)
@@ -183,6 +230,12 @@ def main():
     del Ud
     torch.cuda.empty_cache()
 
+    # the other single-grid workloads of the method (1D, 2D), one context each
+    others = None
+    if not args.no_configs:
+        log("[bench] 1D / 2D configurations")
+        others = other_configs(torch, capi, workloads)
+
     serving = None
     if not args.no_serve:
         # batched serving: 1024 independent 1D/2D Riemann runs arriving as a
@@ -248,6 +301,7 @@ def main():
             "frac_of_hbm_peak": round(path_gbs / HBM_PEAK_GBS, 4),
         },
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
+        "configs_1d_2d": others,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -26,7 +26,8 @@ COPY_KIB = 655360.0  # one 256^3 x 5 FP64 state array
 
 
 # Sources and compile flags that determine the fused 3D stage kernel.
-FUSED_FILES = ("wl2_device.hpp", "wl2_fused.hpp", "wl2_fused_launch.hpp", "wl2_fused3d.hip")
+FUSED_FILES = ("wl2_device.hpp", "wl2_lface.hpp", "wl2_fused.hpp", "wl2_fused_launch.hpp",
+               "wl2_fused3d.hip")
 
 
 def source_hash(files=FUSED_FILES, unit="wl2_fused3d.hip") -> str:
