@@ -98,15 +98,22 @@ __device__ __forceinline__ void roe_light(const LRec<NV>& L, const LRec<NV>& R, 
   s.irho = L.iw * R.iw;
 }
 
-// Linear-branch flux of one face from six light records; returns the mask
-// of fields whose detector asks for the nonlinear flux.
-// `src.get(m, rec)` supplies stencil cell m = 0..5 (j-2 .. j+3); cells are
-// requested in the pairs (0,5), (1,4), (2,3) so only two are live at a time.
-// SPLIT / HYB: compile-time splitting and switch modes, or -1 to read them
-// from ph at run time.
+// Intermediate quantities of a linear face that its nonlinear correction
+// reuses: the Roe state, the splitting speeds, dv = L dU5 / 60 and Fc6.
+template <int NV>
+struct FaceState {
+  Roe<NV> s;
+  double a[NV], dv[NV], Fc6[NV];
+};
+
+// Linear-branch flux of one face from six light records, with its state for
+// a correction; returns the mask of fields whose detector asks for the
+// nonlinear flux.  Cells are requested in the pairs (0,5), (1,4), (2,3) so
+// only two are live at a time.
 template <int NV, int DIR, int SPLIT, int HYB, class Src>
-__device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& ph, double eps_thr,
-                                                  const unsigned long long* lfb, double (&Fh)[NV]) {
+__device__ __forceinline__ unsigned face_linear_st(const Src& src, const KPhys& ph, double eps_thr,
+                                                   const unsigned long long* lfb, double (&Fh)[NV],
+                                                   FaceState<NV>& st) {
   const int split = SPLIT >= 0 ? SPLIT : ph.split;
   const int hybrid = HYB >= 0 ? HYB : ph.hybrid;
   double dU5[NV], Fc6[NV];
@@ -196,7 +203,25 @@ __device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& p
   back_project<NV, DIR>(s, d, Rd);
 #pragma unroll
   for (int i = 0; i < NV; ++i) Fh[i] = Fc6[i] + Rd[i];
+  st.s = s;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    st.a[k] = a[k];
+    st.dv[k] = dv[k];
+    st.Fc6[k] = Fc6[k];
+  }
   return weno;
+}
+
+// Linear-branch flux of one face from six light records; returns the mask
+// of fields whose detector asks for the nonlinear flux.  `src.get(m, rec)`
+// supplies stencil cell m = 0..5 (j-2 .. j+3).  SPLIT / HYB: compile-time
+// splitting and switch modes, or -1 to read them from ph at run time.
+template <int NV, int DIR, int SPLIT, int HYB, class Src>
+__device__ __forceinline__ unsigned face_linear_l(const Src& src, const KPhys& ph, double eps_thr,
+                                                  const unsigned long long* lfb, double (&Fh)[NV]) {
+  FaceState<NV> st;
+  return face_linear_st<NV, DIR, SPLIT, HYB>(src, ph, eps_thr, lfb, Fh, st);
 }
 
 // Index of a line position clamped to [-3, n+2] and mapped through the
@@ -245,65 +270,18 @@ __device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, d
 }
 
 template <int NV, int DIR, class Src>
-__device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, const KPhys& ph,
-                                                const unsigned long long* lfb, double (&dF)[NV]) {
-  double dU5[NV], Fc6[NV];
-  double am = 0.0, a0 = 0.0, ap = 0.0;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) dU5[i] = Fc6[i] = 0.0;
-  constexpr double cu[6] = {1.0, -5.0, 10.0, -10.0, 5.0, -1.0};
-  constexpr double cf[6] = {1.0, -8.0, 37.0, 37.0, -8.0, 1.0};
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    LRec<NV> cm;
-    src.get(m, cm);
-    double F[NV], un;
-    lflux<NV, DIR>(cm, F, un);
-    am = fmax(am, fabs(un - cm.c));
-    a0 = fmax(a0, fabs(un));
-    ap = fmax(ap, fabs(un + cm.c));
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      dU5[i] += cu[m] * cm.U[i];
-      Fc6[i] += cf[m] * F[i];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < NV; ++i) Fc6[i] *= (1.0 / 60.0);
-  Roe<NV> s;
-  {
-    LRec<NV> c2, c3;
-    src.get(2, c2);
-    src.get(3, c3);
-    roe_light<NV, DIR>(c2, c3, ph, s);
-  }
-  double a[NV];
-  if (ph.split == SPLIT_LLF) {
-    a[0] = am;
-#pragma unroll
-    for (int k = 1; k < NV - 1; ++k) a[k] = a0;
-    a[NV - 1] = ap;
-  } else if (ph.split == SPLIT_ROE) {
-    a[0] = fabs(s.u[DIR] - s.c);
-#pragma unroll
-    for (int k = 1; k < NV - 1; ++k) a[k] = fabs(s.u[DIR]);
-    a[NV - 1] = fabs(s.u[DIR] + s.c);
-  } else {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] = __longlong_as_double((long long)lfb[k]);
-  }
-  double dv[NV], LF[NV], del[NV];
-  project<NV, DIR>(s, dU5, dv);
-  project<NV, DIR>(s, Fc6, LF);
+__device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, const FaceState<NV>& st,
+                                                const KPhys& ph, double (&dF)[NV]) {
+  double LF[NV], del[NV];
+  project<NV, DIR>(st.s, st.Fc6, LF);
 #define WL2_LF(K)                                                                            \
   if constexpr (K < NV) {                                                                    \
-    del[K] = ((mask >> K) & 1u)                                                              \
-                 ? lean_field<NV, DIR, K>(src, s, a[K], dv[K] * (1.0 / 60.0), LF[K], ph)    \
-                 : 0.0;                                                                      \
+    del[K] = ((mask >> K) & 1u) ? lean_field<NV, DIR, K>(src, st.s, st.a[K], st.dv[K], LF[K], ph) \
+                                : 0.0;                                                       \
   }
   WL2_LF(0) WL2_LF(1) WL2_LF(2) WL2_LF(3) WL2_LF(4)
 #undef WL2_LF
-  back_project<NV, DIR>(s, del, dF);
+  back_project<NV, DIR>(st.s, del, dF);
 }
 
 // Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
@@ -336,9 +314,10 @@ __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, cons
   }
   const WinSrc<NV> src{w[0], w[1], w[2], w[3], w[4], w[5]};
   double Flin[NV];
-  const unsigned mask = face_linear_l<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin);
+  FaceState<NV> st;
+  const unsigned mask = face_linear_st<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin, st);
   if (mask) {
-    lean_correction<NV, DIR>(src, mask, ph, lfb, dF);
+    lean_correction<NV, DIR>(src, mask, st, ph, dF);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) dF[v] = 0.0;

@@ -249,6 +249,35 @@ def test_3d_advance_folded_cfl(orc, capi, case):
     assert err <= 1e-10
 
 
+def test_2d_rows_per_item_bitwise(capi):
+    """Rows per work item of the fused 1D/2D kernel change no result bit, and
+    the per-direction sweeps agree with it to round-off."""
+    import torch
+    U, dx, bc = make_case("quad67x45")
+    shape = shape_of(U)
+    p = capi.params_default(*shape, dx, bc=bc)
+    outs = []
+    for rows in (0, 1, 5, 16, 45):
+        ctx = capi.Context(*shape, dx, G, p)
+        ctx.tune(capi.PATH_FUSED, rows, 0)
+        Ud = to_dev(U)
+        ctx.advance(Ud, 20, 1e300)
+        torch.cuda.synchronize()
+        outs.append(to_host(Ud))
+        ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ctx = capi.Context(*shape, dx, G, p)
+    ctx.tune(capi.PATH_SWEEPS, 0, 0)
+    Ud = to_dev(U)
+    ctx.advance(Ud, 20, 1e300)
+    torch.cuda.synchronize()
+    err = z20(to_host(Ud), outs[0])
+    ctx.close()
+    say(f"    fused vs sweeps after 20 steps: z20 = {err:.3e}")
+    assert err <= 1e-11
+
+
 def test_degenerate_tiny_grid(orc, capi):
     """Five cells, transmissive left and reflective right wall: one step to
     1e-12; after 100 steps the bound is four times the drift that a one-ulp
