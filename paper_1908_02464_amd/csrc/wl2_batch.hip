@@ -22,7 +22,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int ROW_BLOCKS_DEFAULT = 2048;  // persistent grid of the row kernels
-constexpr int ROWS_DEFAULT = 16;          // rows per work item of a 2D run
+constexpr int ROWS_DEFAULT = 4;           // rows per work item of a 2D run
 constexpr int RED_BLOCKS = 1024;
 
 struct SlotInfo {

@@ -175,14 +175,15 @@ bool use_fused(const weno_l2is_ctx* c) { return c->dim == 3 && c->path != WL2_PA
 bool use_row(const weno_l2is_ctx* c) { return c->dim <= 2 && c->path != WL2_PATH_SWEEPS; }
 
 // Rows per work item of the 1D/2D kernel: the tuned value, else the largest
-// of 32, 16, 8, 4 that still gives >= 2048 items (two per SIMD).
+// of 8, 4, 2 that still gives >= 4096 items (short marches measured faster:
+// the items are single wavefronts and need numbers to hide latency).
 int row_ych(const weno_l2is_ctx* c) {
   if (c->dim == 1) return 1;
   const int cap = ROW_MAX_YCH < c->n[1] ? ROW_MAX_YCH : c->n[1];
   if (c->zchunk > 0) return c->zchunk < cap ? c->zchunk : cap;
   const long long tiles = (c->n[0] + ROW_TILE - 1) / ROW_TILE;
-  int y = 32 < cap ? 32 : cap;
-  while (y > 4 && tiles * ((c->n[1] + y - 1) / y) < 2048) y /= 2;
+  int y = 8 < cap ? 8 : cap;
+  while (y > 2 && tiles * ((c->n[1] + y - 1) / y) < 4096) y /= 2;
   return y;
 }
 
