@@ -43,8 +43,7 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
   }
   const double bm = block_max(smax, sh);
   if (threadIdx.x == 0) {
-    if (bm > 0.0 || bm != bm)
-      atomicMax(&ctl->smax_bits, (unsigned long long)__double_as_longlong(bm));
+    if (bm > 0.0 || bm != bm) cfl_fold(ctl, bm);
   }
   if (bad) atomicOr(&ctl->status, 1u);
 }
@@ -52,10 +51,12 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
 // dt = cfl dx / smax (or a fixed dt), clipped to the device clock when
 // use_clock (dt = 0, a no-op step, once the clock has reached t_end or a
 // non-physical state was seen); resets the running maximum for the next
-// reduction.
+// reduction.  Launched as one wavefront.
 [[maybe_unused]] static __global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / __longlong_as_double((long long)ctl->smax_bits);
+  if (blockIdx.x != 0 || threadIdx.x >= 64) return;
+  const double smax = cfl_take_wave(ctl);  // also resets it for the next reduction
+  if (threadIdx.x != 0) return;
+  double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / smax;
   if (use_clock) {
     // the clock stops at t_end and at the first non-physical state
     const double t = ctl->t, te = ctl->t_end;
@@ -68,7 +69,6 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
     }
   }
   ctl->dt = dt;
-  ctl->smax_bits = 0ull;
 }
 
 // Program the device clock target (enqueued, no host synchronisation) and
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
 [[maybe_unused]] static __global__ void set_t_end_kernel(StepCtl* ctl, double t_end) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl->t_end = t_end;
-    ctl->smax_bits = 0ull;  // a maximum left by an earlier call is stale
+    cfl_clear(ctl);  // a maximum left by an earlier call is stale
   }
 }
 

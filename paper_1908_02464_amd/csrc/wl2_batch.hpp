@@ -78,7 +78,7 @@ __global__ __launch_bounds__(RW, 2) void batch_row_kernel(const BGrid* __restric
     if (!(dt > 0.0)) continue;  // finished (or not started) run
     const StageRefs sr = stage_refs(G, stage);
     const RowArgs a{sr.Uk, sr.out, G.U, G.ctl, sr.ra, sr.rb, list, list_n,
-                    (unsigned long long)it.slot << 40};
+                    (unsigned long long)it.slot << 40, nullptr, nullptr};
     if (G.ph.split == SPLIT_LLF && G.ph.hybrid == HYB_PER_FIELD)
       row_item<NV, OUT_RK, 0, 0>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
     else
@@ -107,11 +107,13 @@ __global__ __launch_bounds__(128) void batch_fix_kernel(const BGrid* __restrict_
     const unsigned cm = (unsigned)(e & 0xffu);
     const bool fast = G.ph.split == SPLIT_LLF && G.ph.hybrid == HYB_PER_FIELD;
     if (G.dim == 1) {
-      if (fast) row_fix_cell<3, 0, 0>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
-      else row_fix_cell<3, -1, -1>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
+      double un[3];
+      if (fast) row_fix_cell<3, 0, 0>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped, un);
+      else row_fix_cell<3, -1, -1>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped, un);
     } else {
-      if (fast) row_fix_cell<4, 0, 0>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
-      else row_fix_cell<4, -1, -1>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped);
+      double un[4];
+      if (fast) row_fix_cell<4, 0, 0>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped, un);
+      else row_fix_cell<4, -1, -1>(sr.Uk, sr.out, G.ctl, G.g, G.ph, off, cm, sr.rb * dt, grouped, un);
     }
   }
 }
@@ -143,8 +145,7 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_cfl_kernel(const BGrid* __res
       }
     }
     const double bm = block_max(smax, sh);
-    if (threadIdx.x == 0 && (bm > 0.0 || bm != bm))
-      atomicMax(&G.ctl->smax_bits, (unsigned long long)__double_as_longlong(bm));
+    if (threadIdx.x == 0 && (bm > 0.0 || bm != bm)) cfl_fold(G.ctl, bm);
     if (bad) atomicOr(&G.ctl->status, 1u);
   }
 }
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_cfl_kernel(const BGrid* __res
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const BGrid& G = grids[slots[i]];
     StepCtl* ctl = G.ctl;
-    double dt = G.cfl_dx / __longlong_as_double((long long)ctl->smax_bits);
+    double dt = G.cfl_dx / cfl_take(ctl);
     const double t = ctl->t, te = ctl->t_end;
     if (!(t < te) || ctl->status != 0u || !(dt > 0.0)) {
       dt = 0.0;
@@ -167,7 +168,6 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_cfl_kernel(const BGrid* __res
       ctl->steps += 1u;
     }
     ctl->dt = dt;
-    ctl->smax_bits = 0ull;
   }
 }
 

@@ -38,6 +38,11 @@ struct weno_l2is_ctx {
   int path;    // WL2_PATH_*
   int zchunk;  // fused kernel: planes per workgroup (0 = automatic)
   int wpe;     // fused kernel: target waves per SIMD (1 or 2)
+  // correction-list counters (ctl->list_n[2]): the stage in flight uses
+  // list_par, its correction kernel clears the other one for the next stage;
+  // both are cleared before the first stage and after a failed launch
+  int list_par = 0;
+  bool list_dirty = true;
   // optional per-launch event timing
   bool timing;
   std::vector<hipEvent_t> ev_pool;
@@ -187,8 +192,32 @@ int row_ych(const weno_l2is_ctx* c) {
   return y;
 }
 
+// The counters of the next stage launch, clearing both if needed.
+struct ListTurn {
+  weno_l2is_ctx* c;
+  unsigned int* cur;
+  unsigned int* next;
+  bool reset;
+  explicit ListTurn(const weno_l2is_ctx* cc) : c(const_cast<weno_l2is_ctx*>(cc)) {
+    cur = &c->ctl->list_n[c->list_par];
+    next = &c->ctl->list_n[c->list_par ^ 1];
+    reset = c->list_dirty;
+  }
+  // after the stage's launches: flip on success, clear both next time if not
+  hipError_t done(hipError_t e) {
+    if (e == hipSuccess) {
+      c->list_par ^= 1;
+      c->list_dirty = false;
+    } else {
+      c->list_dirty = true;
+    }
+    return e;
+  }
+};
+
 hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
-                      const double* Un, double ra, double rb) {
+                      const double* Un, double ra, double rb, bool fold_cfl = false) {
+  ListTurn turn(c);
   RowLaunch L;
   L.Uk = Uk;
   L.out = out;
@@ -201,18 +230,20 @@ hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, do
   L.fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
   L.nvar = c->nvar;
   L.list = c->list;
-  L.list_n = &c->ctl->list_n;
+  L.list_n = turn.cur;
+  L.list_clear = turn.next;
+  L.cfl = fold_cfl ? c->ctl : nullptr;
   L.g = c->g;
   L.ph = c->ph;
   L.stream = c->stream;
-  hipError_t e = row_reset(L);
-  if (e != hipSuccess) return e;
+  hipError_t e = turn.reset ? row_reset(L) : hipSuccess;
+  if (e != hipSuccess) return turn.done(e);
   {
     TimedLaunch tl(c, out_kind == OUT_RK ? "row_rk" : "row_rhs");
-    if ((e = row_launch(L)) != hipSuccess) return e;
+    if ((e = row_launch(L)) != hipSuccess) return turn.done(e);
   }
   TimedLaunch tl(c, "row_fix");
-  return row_fix(L);
+  return turn.done(row_fix(L));
 }
 
 int fused_zchunk(const weno_l2is_ctx* c) {
@@ -226,6 +257,7 @@ int fused_zchunk(const weno_l2is_ctx* c) {
 
 hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
                         const double* Un, double ra, double rb, bool fold_cfl = false) {
+  ListTurn turn(c);
   FusedLaunch L;
   L.Uk = Uk;
   L.out = out;
@@ -233,6 +265,8 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
   L.ctl = c->ctl;
   L.cfl = fold_cfl ? c->ctl : nullptr;
   L.list = c->list;
+  L.list_n = turn.cur;
+  L.list_clear = turn.next;
   L.rk_a = ra;
   L.rk_b = rb;
   L.out_kind = out_kind;
@@ -245,15 +279,15 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
   L.g = c->g;
   L.ph = c->ph;
   L.stream = c->stream;
-  hipError_t e = fused3d_reset(L);
-  if (e != hipSuccess) return e;
+  hipError_t e = turn.reset ? fused3d_reset(L) : hipSuccess;
+  if (e != hipSuccess) return turn.done(e);
   {
     TimedLaunch tl(c, out_kind == OUT_RK ? "fused3d_rk" : "fused3d_rhs");
-    if ((e = fused3d_main(L)) != hipSuccess) return e;
+    if ((e = fused3d_main(L)) != hipSuccess) return turn.done(e);
   }
   // nonlinear corrections of the listed cells (an empty list exits at once)
   TimedLaunch tl(c, "weno_fix3d");
-  return fused3d_fix(L);
+  return turn.done(fused3d_fix(L));
 }
 
 // dU/dt of the state Uk into out (WRITE then ACCUM over directions).
@@ -269,14 +303,15 @@ hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
   return hipSuccess;
 }
 
-// One RK stage: out = a Un + b (Uk + dt L(Uk)).  fold_cfl (fused path): the
-// stage kernels also fold the CFL maximum of `out` into the control word.
+// One RK stage: out = a Un + b (Uk + dt L(Uk)).  fold_cfl (fused 3D and row
+// 1D/2D paths): the stage kernels also fold the CFL maximum of `out` into
+// the control word.
 hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, double* out,
                  double ra, double rb, bool fold_cfl = false) {
   hipError_t e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
-  if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb);
+  if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
   for (int d = 0; d < c->dim - 1; ++d) {
     SweepArgs a{Uk, c->acc, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -417,11 +452,11 @@ int weno_l2is_advance(weno_l2is_ctx* c, double* U, int n_steps, double t_end) {
   if (n_steps < 0 || !(t_end > 0.0) || !std::isfinite(t_end)) return WL2_E_PARAM;
   hipLaunchKernelGGL(set_t_end_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t_end);
   hipError_t e = hipGetLastError();
-  // fused path: the last stage of a step also reduces the CFL speed of the
-  // new state (its cells are in registers there), so every step after the
-  // first of this call skips the separate reduction.  Within one call U is
-  // only touched here, so the folded maximum is that of U.
-  const bool fold = use_fused(c);
+  // fused 3D and row 1D/2D paths: the last stage of a step also reduces the
+  // CFL speed of the new state (its cells are in registers there), so every
+  // step after the first of this call skips the separate reduction.  Within
+  // one call U is only touched here, so the folded maximum is that of U.
+  const bool fold = use_fused(c) || use_row(c);
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     e = launch_cfl(c, U, 0.0, 1, fold && s > 0);
     if (e == hipSuccess) e = rk3(c, U, fold && s + 1 < n_steps);

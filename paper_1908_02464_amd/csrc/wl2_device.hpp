@@ -50,18 +50,71 @@ struct KPhys {
   int split, hybrid;
 };
 
+// One slot of the running CFL maximum (max of sum_d(|u_d|+c) as raw bits;
+// the values are >= 0, so their bit patterns order like the values), alone
+// in its 128-byte line.  The waves of a launch fold into CFL_SLOTS different
+// lines, so that their atomics do not queue on one address.
+constexpr int CFL_SLOTS = 32;
+struct alignas(128) CflSlot {
+  unsigned long long bits;
+};
+
 // Device control block of one grid (time step, clock, status).
 struct StepCtl {
-  unsigned long long smax_bits;  // running max of sum_d(|u_d|+c) as raw bits
   unsigned int status;           // sticky: bit 0 = non-physical state seen
   unsigned int steps;            // clock steps taken (steps that advanced t)
   double dt;                     // dt of the step in flight
   double t;                      // simulated time after the step in flight
   double t_end;                  // > 0: clip the clock to it
   unsigned long long lf_bits[3][5];  // global LF speeds (raw bits) per direction, field
-  unsigned int list_n;           // entries in the nonlinear-correction list
-  unsigned int pad2;
+  unsigned int list_n[2];        // entries in the nonlinear-correction list: consecutive
+                                 // stages alternate between the two counters, and each
+                                 // stage's correction kernel clears the next one's
+  CflSlot smax[CFL_SLOTS];       // running CFL maximum, spread over slots
 };
+
+// Fold a maximum (> 0, or +inf standing for NaN) into the wave's slot.
+__device__ __forceinline__ void cfl_fold(StepCtl* ctl, double m) {
+  const unsigned wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  atomicMax(&ctl->smax[wave % CFL_SLOTS].bits, (unsigned long long)__double_as_longlong(m));
+}
+
+// Clear the running maximum (one thread).
+__device__ __forceinline__ void cfl_clear(StepCtl* ctl) {
+#pragma unroll
+  for (int s = 0; s < CFL_SLOTS; ++s) ctl->smax[s].bits = 0ull;
+}
+
+// The running maximum over all slots, which are cleared for the next
+// reduction (one thread, after the folding launches have finished).
+__device__ __forceinline__ double cfl_take(StepCtl* ctl) {
+  unsigned long long m = 0ull;
+#pragma unroll
+  for (int s = 0; s < CFL_SLOTS; ++s) {
+    const unsigned long long b = ctl->smax[s].bits;
+    m = b > m ? b : m;
+  }
+  cfl_clear(ctl);
+  return __longlong_as_double((long long)m);
+}
+
+// cfl_take by one whole wavefront (lane s reads and clears slot s): one
+// round trip to memory instead of CFL_SLOTS.  Every lane gets the maximum.
+__device__ __forceinline__ double cfl_take_wave(StepCtl* ctl) {
+  static_assert(CFL_SLOTS <= 64, "one slot per lane");
+  const int lane = threadIdx.x & 63;
+  unsigned long long m = 0ull;
+  if (lane < CFL_SLOTS) {
+    m = ctl->smax[lane].bits;
+    ctl->smax[lane].bits = 0ull;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long q = __shfl_xor(m, o, 64);
+    m = q > m ? q : m;
+  }
+  return __longlong_as_double((long long)m);
+}
 
 // ---------------------------------------------------------------- CFL
 // Signal speed sum_d (|u_d| + c) of one cell, in the operation order of the
@@ -90,6 +143,15 @@ __device__ __forceinline__ double cfl_speed(double rho, const double (&m)[DIM], 
   return s;
 }
 
+// cfl_speed of a conserved state u = (rho, momentum, E).
+template <int NV>
+__device__ __forceinline__ double cfl_speed_u(const double (&u)[NV], double gamma, bool& bad) {
+  double m[NV - 2];
+#pragma unroll
+  for (int k = 0; k < NV - 2; ++k) m[k] = u[1 + k];
+  return cfl_speed<NV - 2>(u[0], m, u[NV - 1], gamma, bad);
+}
+
 // Running maximum that lets a NaN win.
 __device__ __forceinline__ double nan_max(double acc, double s) { return (s != s || s > acc) ? s : acc; }
 
@@ -107,7 +169,7 @@ __device__ __forceinline__ void cfl_commit_wave(StepCtl* ctl, double smax, bool 
   const double m = wave_max(nan ? __longlong_as_double(0x7ff0000000000000LL) : smax);
   const unsigned long long anybad = __ballot(bad);
   if ((threadIdx.x & 63) == 0) {
-    if (m > 0.0) atomicMax(&ctl->smax_bits, (unsigned long long)__double_as_longlong(m));
+    if (m > 0.0) cfl_fold(ctl, m);
     if (anybad) atomicOr(&ctl->status, 1u);
   }
 }

@@ -44,8 +44,9 @@ struct FusedArgs {
   int tiles_x, tiles_y;
   unsigned long long* list;  // cells next to a face that needs the WENO flux
   unsigned int* list_n;      // number of entries in list
+  unsigned int* list_clear;  // the next stage's counter, zeroed by the correction kernel
   StepCtl* cfl;              // RK: if set, fold the CFL speed of the new state
-                             // into cfl->smax_bits / status (next step's dt)
+                             // into cfl->smax / status (next step's dt)
 };
 
 template <int NV>
@@ -376,6 +377,8 @@ template <int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
   constexpr int GRP = 8;
+  // the next stage's list starts empty (no kernel of this stage uses it)
+  if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
   double scale = 1.0;
   if (OUT == OUT_RK) {
     const double dt = a.ctl->dt;

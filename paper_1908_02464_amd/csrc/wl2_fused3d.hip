@@ -18,7 +18,8 @@ FusedArgs make_args(const FusedLaunch& L) {
   a.rk_b = L.rk_b;
   a.zc = L.zc;
   a.list = L.list;
-  a.list_n = &L.ctl->list_n;
+  a.list_n = L.list_n;
+  a.list_clear = L.list_clear;
   a.cfl = L.out_kind == OUT_RK ? L.cfl : nullptr;
   a.tiles_x = (L.n[0] + FT_X - 1) / FT_X;
   a.tiles_y = (L.n[1] + FT_Y - 1) / FT_Y;
@@ -28,7 +29,8 @@ FusedArgs make_args(const FusedLaunch& L) {
 }  // namespace
 
 hipError_t fused3d_reset(const FusedLaunch& L) {
-  hipLaunchKernelGGL(reset_list_kernel, dim3(1), dim3(64), 0, L.stream, &L.ctl->list_n);
+  hipLaunchKernelGGL(reset_list_kernel, dim3(1), dim3(64), 0, L.stream, L.list_n);
+  hipLaunchKernelGGL(reset_list_kernel, dim3(1), dim3(64), 0, L.stream, L.list_clear);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ struct FusedLaunch {
   StepCtl* ctl;
   StepCtl* cfl;  // RK stage: fold the CFL speed of the new state into it (or null)
   unsigned long long* list;
+  unsigned int* list_n;      // this stage's list counter
+  unsigned int* list_clear;  // the next stage's, zeroed by the correction kernel
   double rk_a, rk_b;
   int out_kind;  // OUT_WRITE or OUT_RK
   int zc;        // z planes per workgroup
@@ -29,8 +31,10 @@ struct FusedLaunch {
   hipStream_t stream;
 };
 
-// The three launches of one fused stage, in stream order: clear the
-// correction list, the fused stage kernel, the nonlinear corrections.
+// The launches of one fused stage, in stream order: the fused stage kernel
+// and the nonlinear corrections.  The list counter of a stage is cleared by
+// the previous stage's correction kernel; fused3d_reset clears both counters
+// (before the first stage, or after a failed launch).
 hipError_t fused3d_reset(const FusedLaunch& L);
 hipError_t fused3d_main(const FusedLaunch& L);
 hipError_t fused3d_fix(const FusedLaunch& L);

@@ -22,11 +22,15 @@ void launch_nv(const RowLaunch& L, const RowArgs& a, dim3 grid, int ych, int til
 
 hipError_t row_reset(const RowLaunch& L) {
   hipLaunchKernelGGL(row_list_reset_kernel, dim3(1), dim3(64), 0, L.stream, L.list_n);
+  if (L.list_clear != nullptr)
+    hipLaunchKernelGGL(row_list_reset_kernel, dim3(1), dim3(64), 0, L.stream, L.list_clear);
   return hipGetLastError();
 }
 
 hipError_t row_fix(const RowLaunch& L) {
-  const RowArgs a{L.Uk, L.out, L.Un, L.ctl, L.rk_a, L.rk_b, L.list, L.list_n, 0ull};
+  const RowArgs a{L.Uk,   L.out,    L.Un, L.ctl,        L.rk_a,
+                  L.rk_b, L.list,   L.list_n, 0ull, L.list_clear,
+                  L.out_kind == OUT_RK ? L.cfl : nullptr};
   const dim3 fg(1024), fb(128);
 #define WL2_FIX(NV, O)                                                                     \
   do {                                                                                     \
@@ -47,7 +51,9 @@ hipError_t row_fix(const RowLaunch& L) {
 }
 
 hipError_t row_launch(const RowLaunch& L) {
-  const RowArgs a{L.Uk, L.out, L.Un, L.ctl, L.rk_a, L.rk_b, L.list, L.list_n, 0ull};
+  const RowArgs a{L.Uk,   L.out,  L.Un,     L.ctl, L.rk_a,
+                  L.rk_b, L.list, L.list_n, 0ull,  nullptr,
+                  L.out_kind == OUT_RK ? L.cfl : nullptr};
   const int tiles_x = (L.g.n[0] + RT - 1) / RT;
   const int ych = L.nvar == 3 ? 1 : (L.ych < 1 ? 1 : (L.ych > ROW_MAX_YCH ? ROW_MAX_YCH : L.ych));
   const long long chunks = L.nvar == 3 ? 1 : (L.g.n[1] + ych - 1) / ych;

@@ -35,6 +35,10 @@ struct RowArgs {
   unsigned long long* list;  // cells next to a face that needs the WENO flux
   unsigned int* list_n;      // entries in list
   unsigned long long tag;    // or-ed into every entry (the batch slot << 40)
+  unsigned int* list_clear;  // if set: the next stage's counter, zeroed by the
+                             // correction kernel
+  StepCtl* cfl;              // RK: if set, fold the CFL speed of the new state
+                             // into cfl->smax / status (next step's dt)
 };
 
 // Entry of the correction list: tag | element offset << 8 | face mask (bit 0
@@ -157,6 +161,8 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
   const int hx = halo ? ghost_clamped(x0 - 3 + hslot, g.n[0], g.bc_lo[0], g.bc_hi[0], fxh) : 0;
   const long long oxy = cx;  // row 0 element offset of the column (x stride 1)
   const long long hxy = hx;
+  double cfl_max = 0.0;  // CFL speed of the cells written here (a.cfl set)
+  bool cfl_bad = false;
 
   if constexpr (NV == 3) {
     // 1D: one row
@@ -187,8 +193,10 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fr[v] = __shfl_down(Fx[v], 1, RW);
     const unsigned mxr = __shfl_down(mx, 1, RW);
-    list_append(a, oxy, own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u)) : 0u);
+    const unsigned cm = own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u)) : 0u;
+    list_append(a, oxy, cm);
     if (own) {
+      double un[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double dU = (Fx[v] - Fr[v]) * ph.inv_dx;
@@ -196,10 +204,15 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
           double r = a.rk_b * (own_rec.U[v] + dt * dU);
           if (a.rk_a != 0.0) r += a.rk_a * unp[v];
           __builtin_nontemporal_store(r, &a.out[v * g.ncell + oxy]);
+          un[v] = r;
         } else {
           __builtin_nontemporal_store(dU, &a.out[v * g.ncell + oxy]);
         }
       }
+      // a listed cell is finished (and its CFL speed counted) by the
+      // correction kernel
+      if (OUT == OUT_RK && a.cfl != nullptr && cm == 0u)
+        cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
     }
     __syncthreads();  // the buffer is reused by the next item
   } else {
@@ -271,10 +284,12 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fr[v] = __shfl_down(Fx[v], 1, RW);
       const unsigned mxr = __shfl_down(mx, 1, RW);
-      list_append(a, off,
-                  own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u) | (yprev ? 4u : 0u) | (ycur ? 8u : 0u)) : 0u);
+      const unsigned cm =
+          own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u) | (yprev ? 4u : 0u) | (ycur ? 8u : 0u)) : 0u;
+      list_append(a, off, cm);
       yprev = ycur;
       if (own) {
+        double un[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const double dU = ((Fx[v] - Fr[v]) + (Fyp[v] - Fy[v])) * ph.inv_dx;
@@ -282,10 +297,13 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
             double r = a.rk_b * (r0.U[v] + dt * dU);
             if (a.rk_a != 0.0) r += a.rk_a * unp[v];
             __builtin_nontemporal_store(r, &a.out[v * g.ncell + off]);
+            un[v] = r;
           } else {
             __builtin_nontemporal_store(dU, &a.out[v * g.ncell + off]);
           }
         }
+        if (OUT == OUT_RK && a.cfl != nullptr && cm == 0u)
+          cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fyp[v] = Fy[v];
@@ -303,6 +321,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
       __syncthreads();  // row buffer free for the next row
     }
   }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
 // Lanes per listed cell in the correction kernels for short lists (one per
@@ -315,26 +334,33 @@ constexpr int FIX_GRP = 4;
 // grouped: FIX_GRP lanes share the cell (one face each) and the group's first
 // lane writes; else one lane does all.  Each face is recomputed from the
 // stage input by both of its cells with the same operations, so both get
-// the same bits.
+// the same bits.  Returns true on the lane that wrote, with the new state in
+// un.
 template <int NV, int SPLIT, int HYB>
-__device__ __forceinline__ void row_fix_cell(const double* Uk, double* out, const StepCtl* ctl,
+__device__ __forceinline__ bool row_fix_cell(const double* Uk, double* out, const StepCtl* ctl,
                                              const KGrid& g, const KPhys& ph, long long off,
-                                             unsigned cm, double scale, bool grouped) {
+                                             unsigned cm, double scale, bool grouped,
+                                             double (&un)[NV]) {
   const int x = (int)(off % g.n[0]);
   const int y = (int)(off / g.n[0]);
   double acc[NV];
   if (grouped) grouped_correction<NV, FIX_GRP, SPLIT, HYB>(Uk, g, ph, ctl, x, y, 0, cm, acc);
   else serial_correction<NV, SPLIT, HYB>(Uk, g, ph, ctl, x, y, 0, cm, acc);
-  if (!grouped || (threadIdx.x % FIX_GRP) == 0) {
+  if (grouped && (threadIdx.x % FIX_GRP) != 0) return false;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[v * g.ncell + off] += scale * (acc[v] * ph.inv_dx);
+  for (int v = 0; v < NV; ++v) {
+    un[v] = out[v * g.ncell + off] + scale * (acc[v] * ph.inv_dx);
+    out[v * g.ncell + off] = un[v];
   }
+  return true;
 }
 
 // Single grid.  A list that gives every group at most one cell is taken
 // FIX_GRP lanes per cell (latency), a longer one a lane per cell (throughput).
 template <int NV, int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys ph) {
+  // the next stage's list starts empty (no kernel of this stage uses it)
+  if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
   double scale = 1.0;
   if (OUT == OUT_RK) {
     const double dt = a.ctl->dt;
@@ -346,11 +372,18 @@ __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys 
   const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const bool grouped = (unsigned long long)n * FIX_GRP <= FIX_GROUPED_LANES && n <= threads / FIX_GRP;
   const unsigned int step = grouped ? threads / FIX_GRP : threads;
+  double cfl_max = 0.0;
+  bool cfl_bad = false;
   for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
     const unsigned long long e = a.list[i];
-    row_fix_cell<NV, SPLIT, HYB>(a.Uk, a.out, a.ctl, g, ph, (long long)((e >> 8) & 0xffffffffull),
-                                 (unsigned)(e & 0xffu), scale, grouped);
+    double un[NV];
+    const bool wrote = row_fix_cell<NV, SPLIT, HYB>(a.Uk, a.out, a.ctl, g, ph,
+                                                    (long long)((e >> 8) & 0xffffffffull),
+                                                    (unsigned)(e & 0xffu), scale, grouped, un);
+    if (OUT == OUT_RK && a.cfl != nullptr && wrote)
+      cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
   }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
 [[maybe_unused]] static __global__ void row_list_reset_kernel(unsigned int* n) {

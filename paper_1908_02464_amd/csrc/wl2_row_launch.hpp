@@ -21,13 +21,17 @@ struct RowLaunch {
   int nvar;      // 3 (1D) or 4 (2D)
   unsigned long long* list;  // correction list (ncell entries) and its length
   unsigned int* list_n;
+  unsigned int* list_clear;  // the next stage's counter, zeroed by the correction kernel
+  StepCtl* cfl;              // RK: fold the CFL speed of the new state here (or null)
   KGrid g;
   KPhys ph;
   hipStream_t stream;
 };
 
-// The three launches of one stage, in stream order: clear the correction
-// list, the row kernel, the nonlinear corrections of the listed cells.
+// The launches of one stage, in stream order: the row kernel and the
+// nonlinear corrections of the listed cells.  The list counter of a stage is
+// cleared by the previous stage's correction kernel; row_reset clears both
+// counters (before the first stage, or after a failed launch).
 hipError_t row_reset(const RowLaunch& L);
 hipError_t row_launch(const RowLaunch& L);
 hipError_t row_fix(const RowLaunch& L);

@@ -203,18 +203,21 @@ def test_3d_sweeps_path_parity(orc, capi, case):
     assert err <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["turb20x18x17", "turb16x12x10_mixed"])
-def test_3d_advance_folded_cfl(orc, capi, case):
-    """weno_l2is_advance on a 3D grid takes the CFL maximum of U^(n+1) from the
-    last stage kernels (and from the nonlinear-correction kernel for the
-    listed cells) instead of a separate reduction: every dt, and so U, must
-    be bit-identical to steps that reduce U each time; the clock and U match
-    the oracle's own steps."""
-    say(f"[advance-3d] case={case}")
+@pytest.mark.parametrize("case,variant", [
+    ("turb20x18x17", "default"), ("turb16x12x10_mixed", "default"), ("sod200", "default"),
+    ("shu1600", "default"), ("reflect101", "default"), ("quad67x45", "default"),
+    ("quad40x36_mixed", "default"), ("quad67x45", "weno_only"), ("sod200", "linear_only")])
+def test_advance_folded_cfl(orc, capi, case, variant):
+    """weno_l2is_advance takes the CFL maximum of U^(n+1) from the last stage
+    kernels (and from the nonlinear-correction kernel for the listed cells)
+    instead of a separate reduction: every dt, and so U, must be
+    bit-identical to steps that reduce U each time; the clock and U match the
+    oracle's own steps."""
+    say(f"[advance] case={case} variant={variant}")
     import torch
     U, dx, bc = make_case(case)
     shape = shape_of(U)
-    po, pg = params_pair(orc, capi, shape, dx, bc=bc)
+    po, pg = params_pair(orc, capi, shape, dx, bc=bc, **VARIANTS[variant])
     n = 12
     # reference: one step per call (CFL reduced from U every time)
     ctx = capi.Context(*shape, dx, G, pg)
