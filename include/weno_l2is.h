@@ -147,12 +147,16 @@ int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
 /* Kernel path and tuning of a context.  path: WL2_PATH_AUTO or
  * WL2_PATH_FUSED (the single-pass stage kernel of the grid's dimension: 3D
  * column tiles marching in z, or 1D/2D rows of 63 cells marching in y),
- * WL2_PATH_SWEEPS (one kernel per direction, partial sums through memory).
+ * WL2_PATH_SWEEPS (one kernel per direction, partial sums through memory),
+ * WL2_PATH_FUSED_CELLS (the fused stage kernel with the nonlinear
+ * corrections computed per listed cell even where the default corrects
+ * each flagged face once: 2D grids of 131072 cells or more).
  * zchunk: z planes (3D) or rows (2D, at most 62) per work item of the fused
  * kernels (0 = automatic).  waves_per_simd: register budget of the 3D fused
- * kernel, 1 or 2 (0 = default 2).  The two paths agree to round-off; the
- * chunk and register budget change no result bit. */
-enum { WL2_PATH_AUTO = 0, WL2_PATH_SWEEPS = 1, WL2_PATH_FUSED = 2 };
+ * kernel, 1 or 2 (0 = default 2).  The sweeps agree with the fused kernels
+ * to round-off; the chunk, the register budget and the correction mode
+ * change no result bit. */
+enum { WL2_PATH_AUTO = 0, WL2_PATH_SWEEPS = 1, WL2_PATH_FUSED = 2, WL2_PATH_FUSED_CELLS = 3 };
 int weno_l2is_tune(weno_l2is_ctx *ctx, int path, int zchunk, int waves_per_simd);
 
 /* Per-launch kernel timing with HIP events recorded on the context's stream

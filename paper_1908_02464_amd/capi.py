@@ -21,7 +21,7 @@ S_NONPHYSICAL = 1
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
-PATH_AUTO, PATH_SWEEPS, PATH_FUSED = 0, 1, 2
+PATH_AUTO, PATH_SWEEPS, PATH_FUSED, PATH_FUSED_CELLS = 0, 1, 2, 3
 
 
 class WenoL2ISError(RuntimeError):

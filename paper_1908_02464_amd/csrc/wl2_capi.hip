@@ -32,6 +32,8 @@ struct weno_l2is_ctx {
   double* U2;
   double* acc;
   unsigned long long* list;  // cells next to faces needing the WENO flux (fused kernels)
+  double* fo_D = nullptr;          // 2D face-once corrections: face changes per list entry
+  unsigned int* fo_map = nullptr;  // and the cell -> list entry map (null: per-cell kernel)
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
@@ -182,6 +184,12 @@ bool use_row(const weno_l2is_ctx* c) { return c->dim <= 2 && c->path != WL2_PATH
 // Rows per work item of the 1D/2D kernel: the tuned value, else the largest
 // of 8, 4, 2 that still gives >= 4096 items (short marches measured faster:
 // the items are single wavefronts and need numbers to hide latency).
+// 2D grids from this many cells correct their flagged faces once each (two
+// launches) instead of once per adjacent listed cell (one launch): the
+// lists of large grids are long enough for the halved work to outweigh the
+// extra launch.
+constexpr long long FACE_ONCE_MIN_CELLS = 1ll << 17;
+
 int row_ych(const weno_l2is_ctx* c) {
   if (c->dim == 1) return 1;
   const int cap = ROW_MAX_YCH < c->n[1] ? ROW_MAX_YCH : c->n[1];
@@ -233,6 +241,9 @@ hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, do
   L.list_n = turn.cur;
   L.list_clear = turn.next;
   L.cfl = fold_cfl ? c->ctl : nullptr;
+  L.fo_D = c->path == WL2_PATH_FUSED_CELLS ? nullptr : c->fo_D;
+  L.fo_map = c->fo_map;
+  L.fo_cap = (unsigned int)c->ncell;
   L.g = c->g;
   L.ph = c->ph;
   L.stream = c->stream;
@@ -382,12 +393,19 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
             hipMalloc(&c->acc, bytes) == hipSuccess &&
             hipMalloc(&c->ctl, sizeof(StepCtl)) == hipSuccess;
   if (ok) ok = hipMalloc(&c->list, sizeof(unsigned long long) * (size_t)c->ncell) == hipSuccess;
+  if (ok && c->dim == 2 && c->ncell >= FACE_ONCE_MIN_CELLS && c->ncell <= 0xffffffffll)
+    ok = hipMalloc(&c->fo_D, sizeof(double) * 2 * c->nvar * (size_t)c->ncell) == hipSuccess &&
+         hipMalloc(&c->fo_map, sizeof(unsigned int) * (size_t)c->ncell) == hipSuccess &&
+         // every map value stays a valid entry index (< ncell) from the start
+         hipMemsetAsync(c->fo_map, 0, sizeof(unsigned int) * (size_t)c->ncell, c->stream) == hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->U1);
     (void)hipFree(c->U2);
     (void)hipFree(c->acc);
     (void)hipFree(c->list);
+    (void)hipFree(c->fo_D);
+    (void)hipFree(c->fo_map);
     (void)hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
@@ -405,6 +423,8 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   (void)hipFree(c->U2);
   (void)hipFree(c->acc);
   (void)hipFree(c->list);
+  (void)hipFree(c->fo_D);
+  (void)hipFree(c->fo_map);
   (void)hipFree(c->ctl);
   delete c;
 }
@@ -543,7 +563,7 @@ int weno_l2is_status(weno_l2is_ctx* c, unsigned* status_bits, int clear) {
 
 int weno_l2is_tune(weno_l2is_ctx* c, int path, int zchunk, int waves_per_simd) {
   if (!c) return WL2_E_NULL;
-  if (path < WL2_PATH_AUTO || path > WL2_PATH_FUSED || zchunk < 0) return WL2_E_PARAM;
+  if (path < WL2_PATH_AUTO || path > WL2_PATH_FUSED_CELLS || zchunk < 0) return WL2_E_PARAM;
   if (waves_per_simd < 0 || waves_per_simd > 2) return WL2_E_PARAM;
 
   c->path = path;

@@ -32,6 +32,23 @@ hipError_t row_fix(const RowLaunch& L) {
                   L.rk_b, L.list,   L.list_n, 0ull, L.list_clear,
                   L.out_kind == OUT_RK ? L.cfl : nullptr};
   const dim3 fg(1024), fb(128);
+  if (L.fo_D != nullptr) {
+    if (L.nvar != 4) return hipErrorInvalidValue;
+#define WL2_FO(O, S, H)                                                                          \
+  do {                                                                                           \
+    hipLaunchKernelGGL((row_face_kernel<4, O, S, H>), fg, fb, 0, L.stream, a, L.g, L.ph, L.fo_D,  \
+                       L.fo_map, L.fo_cap);                                                      \
+    hipLaunchKernelGGL((row_sum_kernel<4, O, S, H>), fg, fb, 0, L.stream, a, L.g, L.ph, L.fo_D,   \
+                       L.fo_map, L.fo_cap);                                                      \
+  } while (0)
+    if (L.out_kind == OUT_RK) {
+      if (L.fast) WL2_FO(OUT_RK, 0, 0); else WL2_FO(OUT_RK, -1, -1);
+    } else {
+      if (L.fast) WL2_FO(OUT_WRITE, 0, 0); else WL2_FO(OUT_WRITE, -1, -1);
+    }
+#undef WL2_FO
+    return hipGetLastError();
+  }
 #define WL2_FIX(NV, O)                                                                     \
   do {                                                                                     \
     if (L.fast)                                                                            \

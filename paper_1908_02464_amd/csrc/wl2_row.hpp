@@ -386,6 +386,111 @@ __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys 
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
+// Face-once corrections of a long list (single grid).  Every flagged face
+// is shared by two listed cells; the per-cell kernel above computes it for
+// each of them.  Here phase A computes, per listed cell, the flagged face
+// below it in each direction (x-, y-) once, into D[dir][v][entry], and
+// records the cell's entry index in map; phase B sums, per listed cell, its
+// flagged faces in the order x-, x+, y-, y+, taking a face above the cell
+// from the entry of the cell above it (listed, since the face is flagged)
+// or, where that cell is a ghost, computing it.  A face's change of flux has
+// the same bits whichever cell computes it, and the sum is the per-cell
+// kernel's, so the result is bit-identical.
+template <int NV, int OUT, int SPLIT, int HYB>
+__global__ __launch_bounds__(128) void row_face_kernel(RowArgs a, KGrid g, KPhys ph, double* D,
+                                                       unsigned int* map, unsigned int cap) {
+  // the next stage's list starts empty (no kernel of this stage uses it)
+  if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
+  if (OUT == OUT_RK && !(a.ctl->dt > 0.0)) return;
+  constexpr int ND = NV - 2;
+  const unsigned int n = *a.list_n;
+  const unsigned int threads = gridDim.x * blockDim.x;
+  // lanes ordered direction-major, so a wavefront takes faces of one direction
+  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < ND * n; i += threads) {
+    const unsigned int dir = i / n, k = i - dir * n;
+    const unsigned long long e = a.list[k];
+    const long long off = (long long)((e >> 8) & 0xffffffffull);
+    const unsigned cm = (unsigned)(e & 0xffu);
+    if (dir == 0) map[off] = k;
+    if (!((cm >> (2 * dir)) & 1u)) continue;
+    const int x = (int)(off % g.n[0]);
+    const int y = (int)(off / g.n[0]);
+    double dF[NV];
+    if (dir == 0) {
+      face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, 0, 0, dF);
+    } else {
+      if constexpr (NV >= 4)
+        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, 0, 0, dF);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) D[((size_t)dir * NV + v) * cap + k] = dF[v];
+  }
+}
+
+template <int NV, int OUT, int SPLIT, int HYB>
+__global__ __launch_bounds__(128) void row_sum_kernel(RowArgs a, KGrid g, KPhys ph,
+                                                      const double* __restrict__ D,
+                                                      const unsigned int* __restrict__ map,
+                                                      unsigned int cap) {
+  double scale = 1.0;
+  if (OUT == OUT_RK) {
+    const double dt = a.ctl->dt;
+    if (!(dt > 0.0)) return;
+    scale = a.rk_b * dt;
+  }
+  constexpr int ND = NV - 2;
+  const unsigned int n = *a.list_n;
+  const unsigned int threads = gridDim.x * blockDim.x;
+  double cfl_max = 0.0;
+  bool cfl_bad = false;
+  for (unsigned int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += threads) {
+    const unsigned long long e = a.list[k];
+    const long long off = (long long)((e >> 8) & 0xffffffffull);
+    const unsigned cm = (unsigned)(e & 0xffu);
+    const int x = (int)(off % g.n[0]);
+    const int y = (int)(off / g.n[0]);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int f = 0; f < 2 * ND; ++f) {
+      if (!((cm >> f) & 1u)) continue;
+      const int dir = f >> 1, side = f & 1;
+      double d[NV];
+      if (side == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) d[v] = D[((size_t)dir * NV + v) * cap + k];
+      } else {
+        const int pos = dir == 0 ? x : y;
+        if (pos + 1 < g.n[dir]) {
+          // the cell above is listed in this stage (its face below is the
+          // flagged face); min() only keeps a broken list inside D
+          const unsigned int kk = min(map[off + (dir == 0 ? 1ll : g.stride[1])], cap - 1u);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) d[v] = D[((size_t)dir * NV + v) * cap + kk];
+        } else if (dir == 0) {
+          face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, 0, 1, d);
+        } else {
+          if constexpr (NV >= 4)
+            face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, 0, 1, d);
+        }
+      }
+      const double sg = side ? -1.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sg * d[v];
+    }
+    double un[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      un[v] = a.out[v * g.ncell + off] + scale * (acc[v] * ph.inv_dx);
+      a.out[v * g.ncell + off] = un[v];
+    }
+    if (OUT == OUT_RK && a.cfl != nullptr)
+      cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
+  }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
+}
+
 [[maybe_unused]] static __global__ void row_list_reset_kernel(unsigned int* n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *n = 0u;
 }

@@ -23,6 +23,11 @@ struct RowLaunch {
   unsigned int* list_n;
   unsigned int* list_clear;  // the next stage's counter, zeroed by the correction kernel
   StepCtl* cfl;              // RK: fold the CFL speed of the new state here (or null)
+  // face-once corrections (2D, long lists): per-entry face changes
+  // [2][nvar][fo_cap] and the cell -> entry map [ncell]; null: per cell
+  double* fo_D;
+  unsigned int* fo_map;
+  unsigned int fo_cap;
   KGrid g;
   KPhys ph;
   hipStream_t stream;

@@ -281,6 +281,36 @@ def test_2d_rows_per_item_bitwise(capi):
     assert err <= 1e-11
 
 
+@pytest.mark.parametrize("bc,variant,steps", [
+    ([1, 1, 1, 1, 1, 1], "default", 10), ([0, 0, 2, 2, 1, 1], "weno_only", 3),
+    ([2, 2, 0, 0, 1, 1], "per_face", 5), ([1, 2, 2, 1, 1, 1], "lf", 3)])
+def test_2d_face_once_bitwise(capi, bc, variant, steps):
+    """On 2D grids of 131072 cells or more each flagged face is corrected once
+    (two kernels sharing per-face results through a cell -> entry map); the
+    result must equal, bit for bit, the per-cell correction kernel, with
+    every boundary kind on the high sides (where the face above a cell is
+    computed in place)."""
+    import torch
+    U, dx, _ = w.four_quadrant_2d(520, 300, 31)
+    shape = (520, 300, 1)
+    p = capi.params_default(*shape, dx, bc=bc, **VARIANTS[variant])
+    outs, clocks = [], []
+    for path in (capi.PATH_FUSED, capi.PATH_FUSED_CELLS):
+        ctx = capi.Context(*shape, dx, G, p)
+        ctx.tune(path, 0, 0)
+        Ud = to_dev(U)
+        ctx.advance(Ud, steps, 1e300)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        outs.append(to_host(Ud))
+        clocks.append(ctx.clock())
+        ctx.close()
+    d = float(np.abs(outs[0] - outs[1]).max())
+    say(f"    face-once vs per-cell after {steps} steps: max|diff| = {d:.3e}")
+    assert clocks[0] == clocks[1]
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_degenerate_tiny_grid(orc, capi):
     """Five cells, transmissive left and reflective right wall: one step to
     1e-12; after 100 steps the bound is four times the drift that a one-ulp
