@@ -36,17 +36,17 @@ def log(*a):
 PROFILE = os.path.join(ROOT, "profiles", "fused3d_rk_turbulence256.md")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the stage kernel from the committed rocprofv3
-    counter summary, or None if it is missing or the kernel sources changed
-    since the counters were taken."""
+def measured_profile():
+    """The committed rocprofv3 counter summary of the stage kernel (HBM bytes
+    and FP64 operations per launch), or (None, reason) if it is missing or
+    the kernel sources changed since the counters were taken."""
     try:
         from paper_1908_02464_amd.rocprof_summary import source_hash
         txt = open(PROFILE).read()
         info = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
         if info.get("source_hash") != source_hash():
             return None, "stale"
-        return info.get("traffic_bytes_per_launch"), info.get("source_hash")
+        return info, info.get("source_hash")
     except (OSError, ValueError, IndexError, KeyError):
         return None, "missing"
 
@@ -70,6 +70,38 @@ def cpu_baseline(U0, dx, min_seconds=10.0):
             "kind": "oracle",
             "sample": f"{steps} SSP-RK3 steps of the oracle on a {nx}x{ny}x{nz} slab of the same "
                       f"256^3 initial field ({el:.1f} s, single thread)"}
+
+
+def variants_3d(torch, capi, U0, dx, steps=10):
+    """The same 256^3 field with every face on the WENO-L2IS branch (switch
+    off) and with every face on the linear branch (switch forced), timed like
+    the headline after two warm-up steps: the two ends between which the
+    hybrid scheme's cost lies."""
+    out = {}
+    for name, hyb in (("weno_only", 2), ("linear_only", 3)):
+        p = capi.params_default(N, N, N, dx, bc=[0] * 6, hybrid=hyb)
+        ctx = capi.Context(N, N, N, dx, GAMMA, p)
+        Ud = torch.from_numpy(U0).cuda()
+        ctx.advance(Ud, 2, 1e300)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.advance(Ud, steps, 1e300)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        ctx.timing(True)
+        ctx.advance(Ud, 2, 1e300)
+        kt = ctx.timing_read()
+        ctx.timing(False)
+        out[name] = {"steps": steps, "ms_per_step": round(ms / steps, 4),
+                     "Mcell_updates_per_s_per_stage": round(N ** 3 * 3 * steps / (ms * 1e-3) / 1e6, 2),
+                     "kernel_ms_per_step": {k: round(v[0] / 2, 4) for k, v in kt.items()},
+                     "status": ctx.status()}
+        log(f"[bench]   3D {name}: {out[name]['ms_per_step']} ms/step")
+        ctx.close()
+        del Ud
+        torch.cuda.empty_cache()
+    return out
 
 
 def other_configs(torch, capi, workloads):
@@ -131,6 +163,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 1D / 2D single-grid workloads")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the 3D WENO-only / linear-only timings")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the batched-serving leg (Poisson stream of 1D/2D Riemann runs)")
     ap.add_argument("--serve-requests", type=int, default=1024)
@@ -201,9 +235,12 @@ def main():
                    "sweep_x_accum": 3.0, "sweep_y_write": 2.0, "sweep_z_accum": 3.0}
     dom_bytes = role_arrays.get(dom, 2.0) * arr
     achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
-    traffic, traffic_src = (None, "n/a")
+    traffic, traffic_src, flops = (None, "n/a", None)
     if dom == "fused3d_rk":
-        traffic, traffic_src = measured_traffic()
+        prof, traffic_src = measured_profile()
+        if prof is not None:
+            traffic = prof.get("traffic_bytes_per_launch")
+            flops = prof.get("fp64_flops_per_launch")
     # the method's own bytes per cell-stage: 8/3 state arrays (read U^(k), U^n,
     # write U^(k+1); stage 1 reads only U^n)
     path_bytes = 8.0 / 3.0 * nvar * 8
@@ -229,6 +266,11 @@ def main():
     ctx.close()
     del Ud
     torch.cuda.empty_cache()
+
+    variants = None
+    if not args.no_variants and args.hybrid == 0 and args.path == 0:
+        log("[bench] 3D WENO-only / linear-only variants")
+        variants = variants_3d(torch, capi, U0, dx)
 
     # the other single-grid workloads of the method (1D, 2D), one context each
     others = None
@@ -295,6 +337,16 @@ def main():
             "launches": dom_n,
             "algorithmic_bytes_per_launch": int(dom_bytes),
         },
+        # counted FP64 VALU operations of the stage kernel (committed counter
+        # summary, same source hash) over its event-timed launch duration
+        "fp64_valu": ({
+            "flops_per_launch": round(flops),
+            "achieved_tflops": round(flops / (avg_ms * 1e-3) / 1e12, 2),
+            "peak_tflops": FP64_VECTOR_TFLOPS,
+            "frac": round(flops / (avg_ms * 1e-3) / 1e12 / FP64_VECTOR_TFLOPS, 4),
+            "flops_per_cell_stage": round(flops / ncell, 1),
+        } if flops else None),
+        "variants_3d": variants,
         "path_roofline": {
             "bytes_per_cell_stage": round(path_bytes, 2),
             "achieved_GBs": round(path_gbs, 1),

@@ -8,6 +8,10 @@ Usage (after a kernel-trace run and two counter runs of the same command):
 FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are scaled by what the same
 counters read for the device copy of one 655360 KiB state array in the same
 runs (bench.py --copy-calibration), so the reported traffic is in bytes.
+With --valu DIR (a run with the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64,
+SQ_INSTS_VALU and SQ_WAVES counters) the FP64 operations per dispatch are
+added: 64 lanes x (2 FMA + ADD + MUL + TRANS) wave instructions, i.e. every
+lane counted (inactive lanes of a partial wave included).
 The summary records a hash of the kernel sources so that stale counter
 numbers are recognised.
 """
@@ -76,6 +80,7 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
+    ap.add_argument("--valu")
     ap.add_argument("--command", required=True)
     ap.add_argument("--workload", default="3D Euler turbulence 256^3 periodic, FP64")
     ap.add_argument("--out", required=True)
@@ -98,6 +103,19 @@ def main():
         if ff and wf:
             info["traffic_bytes_per_launch"] = (statistics.mean(fv) * ff +
                                                 statistics.mean(wv) * wf) * 1024.0
+    if a.valu:
+        v = {}
+        for name in ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                     "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU", "SQ_WAVES"):
+            vals, _ = counter(a.valu, a.kernel, name)
+            if vals:
+                v[name + "_per_dispatch"] = statistics.mean(vals)
+        info["valu"] = v
+        need = ("SQ_INSTS_VALU_ADD_F64_per_dispatch", "SQ_INSTS_VALU_MUL_F64_per_dispatch",
+                "SQ_INSTS_VALU_FMA_F64_per_dispatch", "SQ_INSTS_VALU_TRANS_F64_per_dispatch")
+        if all(k in v for k in need):
+            info["fp64_flops_per_launch"] = 64.0 * (2.0 * v[need[2]] + v[need[0]] + v[need[1]] +
+                                                    v[need[3]])
     lines = ["# rocprofv3 summary: " + a.kernel, "",
              "command: " + a.command, "",
              "```json", json.dumps(info, indent=1), "```", ""]
