@@ -181,22 +181,24 @@ hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
 bool use_fused(const weno_l2is_ctx* c) { return c->dim == 3 && c->path != WL2_PATH_SWEEPS; }
 bool use_row(const weno_l2is_ctx* c) { return c->dim <= 2 && c->path != WL2_PATH_SWEEPS; }
 
-// Rows per work item of the 1D/2D kernel: the tuned value, else the largest
-// of 8, 4, 2 that still gives >= 4096 items (short marches measured faster:
-// the items are single wavefronts and need numbers to hide latency).
 // 2D grids from this many cells correct their flagged faces once each (two
 // launches) instead of once per adjacent listed cell (one launch): the
 // lists of large grids are long enough for the halved work to outweigh the
 // extra launch.
 constexpr long long FACE_ONCE_MIN_CELLS = 1ll << 17;
 
+// Rows per work item of the 1D/2D kernel: the tuned value, else the largest
+// of 6 .. 2 that still gives >= 1536 items, three quarters of the 2048
+// wavefronts the chip holds at once (measured: 6 rows at 1024^2 and 2048^2,
+// 3 at 512^2, 2 at 256^2; longer marches amortise the six-cell start of a
+// column, more items fill the chip).
 int row_ych(const weno_l2is_ctx* c) {
   if (c->dim == 1) return 1;
   const int cap = ROW_MAX_YCH < c->n[1] ? ROW_MAX_YCH : c->n[1];
   if (c->zchunk > 0) return c->zchunk < cap ? c->zchunk : cap;
   const long long tiles = (c->n[0] + ROW_TILE - 1) / ROW_TILE;
-  int y = 8 < cap ? 8 : cap;
-  while (y > 2 && tiles * ((c->n[1] + y - 1) / y) < 4096) y /= 2;
+  int y = 6 < cap ? 6 : cap;
+  while (y > 2 && tiles * ((c->n[1] + y - 1) / y) < 1536) --y;
   return y;
 }
 
