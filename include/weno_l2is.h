@@ -113,7 +113,12 @@ int weno_l2is_step(weno_l2is_ctx *ctx, double *U, double dt);
  * exactly at t_end (> 0; the last step is clipped, later steps are no-ops).
  * Steps after a non-physical state was seen (status bit set) are no-ops too:
  * U keeps the last state the CFL reduction flagged.
- * The simulated time is kept on the device and read by weno_l2is_time. */
+ * The simulated time is kept on the device and read by weno_l2is_time.
+ * The result equals n_steps calls of weno_l2is_step with the clock rule, bit
+ * for bit; internally the CFL maximum of a step is folded out of the
+ * previous step's last stage, and 1D grids of up to 1024 cells (not with
+ * global Lax-Friedrichs splitting) run all steps in one single-workgroup
+ * launch.  Asynchronous on the context's stream. */
 int weno_l2is_advance(weno_l2is_ctx *ctx, double *U, int n_steps,
                       double t_end);
 

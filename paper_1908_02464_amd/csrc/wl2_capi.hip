@@ -180,6 +180,11 @@ hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
 
 bool use_fused(const weno_l2is_ctx* c) { return c->dim == 3 && c->path != WL2_PATH_SWEEPS; }
 bool use_row(const weno_l2is_ctx* c) { return c->dim <= 2 && c->path != WL2_PATH_SWEEPS; }
+// advance() of a small 1D grid runs in one single-workgroup launch (not with
+// global Lax-Friedrichs speeds, which need a grid-wide reduction per stage)
+bool use_row_steps(const weno_l2is_ctx* c) {
+  return c->dim == 1 && use_row(c) && c->n[0] <= ROW_STEPS_MAX_CELLS && c->p.split != WL2_SPLIT_LF;
+}
 
 // 2D grids from this many cells correct their flagged faces once each (two
 // launches) instead of once per adjacent listed cell (one launch): the
@@ -474,6 +479,13 @@ int weno_l2is_advance(weno_l2is_ctx* c, double* U, int n_steps, double t_end) {
   if (n_steps < 0 || !(t_end > 0.0) || !std::isfinite(t_end)) return WL2_E_PARAM;
   hipLaunchKernelGGL(set_t_end_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t_end);
   hipError_t e = hipGetLastError();
+  // small 1D grids: every step in one single-workgroup launch
+  if (e == hipSuccess && use_row_steps(c)) {
+    TimedLaunch tl(c, "row1d_steps");
+    return hip_err(row1d_steps(U, c->U1, c->U2, c->ctl, c->list, c->p.cfl * c->dx, n_steps,
+                               c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD,
+                               c->g, c->ph, c->stream));
+  }
   // fused 3D and row 1D/2D paths: the last stage of a step also reduces the
   // CFL speed of the new state (its cells are in registers there), so every
   // step after the first of this call skips the separate reduction.  Within

@@ -27,6 +27,19 @@ hipError_t row_reset(const RowLaunch& L) {
   return hipGetLastError();
 }
 
+hipError_t row1d_steps(double* U, double* U1, double* U2, StepCtl* ctl, unsigned long long* list,
+                       double cfl_dx, int n_steps, int fast, const KGrid& g, const KPhys& ph,
+                       hipStream_t stream) {
+  constexpr int W = 8;
+  if (g.n[1] != 1 || g.n[2] != 1 || g.n[0] > ROW_STEPS_MAX_CELLS) return hipErrorInvalidValue;
+  const RowStepsArgs s{U, U1, U2, ctl, list, cfl_dx, n_steps};
+  if (fast)
+    hipLaunchKernelGGL((row1d_steps_kernel<W, 0, 0>), dim3(1), dim3(W * RW), 0, stream, s, g, ph);
+  else
+    hipLaunchKernelGGL((row1d_steps_kernel<W, -1, -1>), dim3(1), dim3(W * RW), 0, stream, s, g, ph);
+  return hipGetLastError();
+}
+
 hipError_t row_fix(const RowLaunch& L) {
   const RowArgs a{L.Uk,   L.out,    L.Un, L.ctl,        L.rk_a,
                   L.rk_b, L.list,   L.list_n, 0ull, L.list_clear,

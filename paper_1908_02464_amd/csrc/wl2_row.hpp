@@ -491,6 +491,99 @@ __global__ __launch_bounds__(128) void row_sum_kernel(RowArgs a, KGrid g, KPhys 
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
+// Small 1D grids: whole SSP-RK3 steps in one workgroup of W wavefronts and
+// one launch (the launches of the stage kernels, not their work, bound such
+// grids).  Per step: the CFL maximum of U (cfl_speed, an exact maximum),
+// the clock rule of finalize_dt_kernel, then per stage the row items (item
+// k on wavefront k mod W, every wavefront taking the same number of items,
+// past the grid edge owning no cell) and the corrections of the listed
+// cells, with workgroup barriers between.  The same row_item and
+// row_fix_cell code as the multi-launch path: the same bits.
+struct RowStepsArgs {
+  double* U;             // state, advanced in place
+  double* U1;            // stage states
+  double* U2;
+  StepCtl* ctl;          // clock, t_end, status, dt
+  unsigned long long* list;
+  double cfl_dx;         // CFL number x dx
+  int n_steps;
+};
+
+template <int W, int SPLIT, int HYB>
+__global__ __launch_bounds__(W * RW) void row1d_steps_kernel(RowStepsArgs s, KGrid g, KPhys ph) {
+  constexpr int NV = 3;
+  __shared__ double buf[W][NV + 3][RB];
+  __shared__ double red[W];
+  __shared__ unsigned int flags;  // bit 0: a non-physical cell in U
+  __shared__ unsigned int list_n;
+  __shared__ double s_dt;
+  const int wave = threadIdx.x / RW, lane = threadIdx.x % RW;
+  const int nthr = W * RW;
+  const int n = g.n[0];
+  const int per_wave = ((n + RT - 1) / RT + W - 1) / W;
+  StepCtl* ctl = s.ctl;
+  for (int step = 0; step < s.n_steps; ++step) {
+    double m = 0.0;
+    bool bad = false;
+    for (int c = threadIdx.x; c < n; c += nthr) {
+      double u[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = s.U[v * g.ncell + c];
+      m = nan_max(m, cfl_speed_u<NV>(u, ph.gamma, bad));
+    }
+    // a NaN maximum is raised to +inf so that it wins (as in every reduction)
+    const double wm = wave_max(m != m ? __longlong_as_double(0x7ff0000000000000LL) : m);
+    const unsigned long long anybad = __ballot(bad);
+    if (threadIdx.x == 0) flags = 0u;
+    if (lane == 0) red[wave] = wm;
+    __syncthreads();
+    if (lane == 0 && anybad) atomicOr(&flags, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double smax = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) smax = fmax(smax, red[w]);
+      if (flags) ctl->status |= 1u;
+      double dt = s.cfl_dx / smax;
+      const double t = ctl->t, te = ctl->t_end;
+      if (!(t < te) || ctl->status != 0u) {
+        dt = 0.0;
+      } else {
+        if (t + dt > te) dt = te - t;
+        ctl->t = t + dt;
+        ctl->steps += 1u;
+      }
+      ctl->dt = dt;
+      s_dt = dt;
+    }
+    __syncthreads();
+    const double dt = s_dt;
+    if (!(dt > 0.0)) break;  // the clock has stopped (uniform)
+    for (int st = 0; st < 3; ++st) {
+      const double* Uk = st == 0 ? s.U : (st == 1 ? s.U1 : s.U2);
+      double* out = st == 0 ? s.U1 : (st == 1 ? s.U2 : s.U);
+      const double ra = st == 0 ? 0.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
+      const double rb = st == 0 ? 1.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
+      if (threadIdx.x == 0) list_n = 0u;
+      __syncthreads();
+      const RowArgs a{Uk, out, s.U, ctl, ra, rb, s.list, &list_n, 0ull, nullptr, nullptr};
+      for (int k = 0; k < per_wave; ++k)
+        row_item<NV, OUT_RK, SPLIT, HYB>(a, g, ph, buf[wave], nullptr, (wave + k * W) * RT, 0, 1, dt);
+      __syncthreads();
+      const unsigned int nl = list_n;
+      const bool grouped = (unsigned long long)nl * FIX_GRP <= (unsigned long long)nthr;
+      const unsigned int stride = grouped ? nthr / FIX_GRP : nthr;
+      for (unsigned int i = grouped ? threadIdx.x / FIX_GRP : threadIdx.x; i < nl; i += stride) {
+        const unsigned long long e = s.list[i];
+        double un[NV];
+        row_fix_cell<NV, SPLIT, HYB>(Uk, out, ctl, g, ph, (long long)((e >> 8) & 0xffffffffull),
+                                     (unsigned)(e & 0xffu), rb * dt, grouped, un);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 [[maybe_unused]] static __global__ void row_list_reset_kernel(unsigned int* n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *n = 0u;
 }

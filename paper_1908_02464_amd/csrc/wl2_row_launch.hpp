@@ -41,4 +41,14 @@ hipError_t row_reset(const RowLaunch& L);
 hipError_t row_launch(const RowLaunch& L);
 hipError_t row_fix(const RowLaunch& L);
 
+// Small 1D grids: n_steps clock steps of U (SSP-RK3, device CFL dt, the
+// clock rule of the multi-launch path) in one single-workgroup launch of
+// eight wavefronts (measured per step against seven launches: 200 cells
+// 19 vs 33 us, 800 cells 26 vs 34 us, 1024 cells 31 vs 33 us, 1600 cells
+// 38 vs 35 us; sixteen wavefronts spill).
+constexpr int ROW_STEPS_MAX_CELLS = 1024;
+hipError_t row1d_steps(double* U, double* U1, double* U2, StepCtl* ctl, unsigned long long* list,
+                       double cfl_dx, int n_steps, int fast, const KGrid& g, const KPhys& ph,
+                       hipStream_t stream);
+
 }  // namespace wl2

@@ -206,13 +206,16 @@ def test_3d_sweeps_path_parity(orc, capi, case):
 @pytest.mark.parametrize("case,variant", [
     ("turb20x18x17", "default"), ("turb16x12x10_mixed", "default"), ("sod200", "default"),
     ("shu1600", "default"), ("reflect101", "default"), ("quad67x45", "default"),
-    ("quad40x36_mixed", "default"), ("quad67x45", "weno_only"), ("sod200", "linear_only")])
+    ("quad40x36_mixed", "default"), ("quad67x45", "weno_only"), ("sod200", "linear_only"),
+    ("sod200", "weno_only"), ("shu1600", "roe"), ("adv128", "default"), ("tiny5", "default"),
+    ("sod200", "lf")])
 def test_advance_folded_cfl(orc, capi, case, variant):
     """weno_l2is_advance takes the CFL maximum of U^(n+1) from the last stage
     kernels (and from the nonlinear-correction kernel for the listed cells)
-    instead of a separate reduction: every dt, and so U, must be
-    bit-identical to steps that reduce U each time; the clock and U match the
-    oracle's own steps."""
+    instead of a separate reduction, and runs small 1D grids in one
+    single-workgroup launch: every dt, and so U, must be bit-identical to
+    steps that reduce U each time; the clock and U match the oracle's own
+    steps."""
     say(f"[advance] case={case} variant={variant}")
     import torch
     U, dx, bc = make_case(case)
@@ -354,6 +357,28 @@ def test_advance_to_t_end(orc, capi):
     say(f"    steps={n} t_oracle={t} t_gpu={tg} z20={z20(got, Uo):.3e}")
     assert tg == 0.2 and t == 0.2
     assert z20(got, Uo) <= 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [128, 5000])
+def test_advance_stops_at_nonphysical(capi, n):
+    """advance() on a state with a non-physical cell takes no step: the status
+    is set, the clock and the state stay as they were (1D grids up to 1024
+    cells run in the single-workgroup kernel, larger ones in the stage
+    kernels)."""
+    import torch
+    U, dx = w.sod(n)
+    U = U.copy()
+    U[2, 0, 0, n // 3] = -1.0
+    ctx = capi.Context(n, 1, 1, dx)
+    Ud = to_dev(U)
+    ctx.set_time(0.0)
+    ctx.advance(Ud, 10, 0.2)
+    torch.cuda.synchronize()
+    t, dt, steps = ctx.clock()
+    assert ctx.status() & 1
+    assert t == 0.0 and steps == 0 and dt == 0.0
+    assert np.array_equal(to_host(Ud).reshape(U.shape), U)
     ctx.close()
 
 
