@@ -163,7 +163,7 @@ __device__ __forceinline__ unsigned face_linear_st(const Src& src, const KPhys& 
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       dU5[i] += 10.0 * (c2.U[i] - c3.U[i]);
-      Fc6[i] = (Fc6[i] + 37.0 * (F2[i] + F3[i])) * (1.0 / 60.0);
+      Fc6[i] += 37.0 * (F2[i] + F3[i]);  // 60 Fc6: the 1/60 is applied below
     }
   }
   Roe<NV> s;
@@ -183,18 +183,31 @@ __device__ __forceinline__ unsigned face_linear_st(const Src& src, const KPhys& 
 #pragma unroll
     for (int k = 0; k < NV; ++k) a[k] = __longlong_as_double((long long)lfb[k]);
   }
-  double dv[NV], d[NV];
+  // dv = L dU5 / 60 and Fc6 enter scaled by 60; the 1/60 is folded into
+  // the detector scale, the splitting speeds and the final flux
+  constexpr double k60 = 1.0 / 60.0;
+  double dv[NV], d[NV], a60[NV];
   project<NV, DIR>(s, dU5, dv);
+  const double irho60 = s.irho * k60;
+  if (split == SPLIT_LLF) {
+    const double am60 = a[0] * k60, a060 = a[1] * k60, ap60 = a[NV - 1] * k60;
+    a60[0] = am60;
+#pragma unroll
+    for (int k = 1; k < NV - 1; ++k) a60[k] = a060;
+    a60[NV - 1] = ap60;
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a60[k] = a[k] * k60;
+  }
   unsigned weno = 0;
   double smax = 0.0;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    dv[k] *= (1.0 / 60.0);
-    const double t = dv[k] * s.irho;
+    const double t = dv[k] * irho60;
     const double sig = t * t;  // Eq.(30)
     smax = fmax(smax, sig);
     if (!(sig < eps_thr)) weno |= 1u << k;
-    d[k] = a[k] * dv[k];
+    d[k] = a60[k] * dv[k];
   }
   if (hybrid == HYB_PER_FACE) weno = (smax < eps_thr) ? 0u : ((1u << NV) - 1u);
   else if (hybrid == HYB_WENO_ONLY) weno = (1u << NV) - 1u;
@@ -202,13 +215,15 @@ __device__ __forceinline__ unsigned face_linear_st(const Src& src, const KPhys& 
   double Rd[NV];
   back_project<NV, DIR>(s, d, Rd);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) Fh[i] = Fc6[i] + Rd[i];
+  for (int i = 0; i < NV; ++i) Fh[i] = Fc6[i] * k60 + Rd[i];
+  // the state in the paper's units for a nonlinear correction (dead code,
+  // removed by the compiler, where the caller drops it)
   st.s = s;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     st.a[k] = a[k];
-    st.dv[k] = dv[k];
-    st.Fc6[k] = Fc6[k];
+    st.dv[k] = dv[k] * k60;
+    st.Fc6[k] = Fc6[k] * k60;
   }
   return weno;
 }
