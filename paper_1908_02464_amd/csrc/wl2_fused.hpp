@@ -26,6 +26,11 @@ constexpr int FT_THREADS = 256;
 constexpr int FT_OWN = FT_X * FT_Y;              // 240 column owners
 constexpr int FP_X = FT_X + 6, FP_Y = FT_Y + 6;  // LDS plane pitch (with halo)
 constexpr int FP_N = FP_X * FP_Y;
+// LDS plane layout: row-major cells, the eight record values of a row
+// interleaved (row, value, column), so the 48 values of an x-face stencil
+// lie within the immediate-offset reach of one LDS address (a y-face
+// stencil within four) instead of one address per value plane.
+constexpr int FP_ROW = 8 * FP_X;  // doubles per LDS row (NV + 3 = 8 values)
 constexpr int NXF = (FT_X + 1) * FT_Y;           // 255 x faces per plane
 constexpr int NYF = FT_X * (FT_Y + 1);           // 256 y faces per plane
 constexpr int NHALO = 6 * FT_Y + 6 * FT_X;       // 186 halo cells per plane
@@ -50,32 +55,42 @@ struct FusedArgs {
 };
 
 template <int NV>
-__device__ __forceinline__ void lds_put(double (*srec)[FP_N], int idx, const LRec<NV>& r) {
+__device__ __forceinline__ void lds_put(double* srec, int idx, const LRec<NV>& r) {
+  static_assert(NV + 3 == 8, "eight values per LDS cell");
 #pragma unroll
-  for (int v = 0; v < NV; ++v) srec[v][idx] = r.U[v];
-  srec[NV][idx] = r.p;
-  srec[NV + 1][idx] = r.c;
-  srec[NV + 2][idx] = r.iw;
+  for (int v = 0; v < NV; ++v) srec[idx + v * FP_X] = r.U[v];
+  srec[idx + NV * FP_X] = r.p;
+  srec[idx + (NV + 1) * FP_X] = r.c;
+  srec[idx + (NV + 2) * FP_X] = r.iw;
 }
 
-template <int NV>
-__device__ __forceinline__ void lds_get(double (*srec)[FP_N], int idx, LRec<NV>& r) {
-#pragma unroll
-  for (int v = 0; v < NV; ++v) r.U[v] = srec[v][idx];
-  r.p = srec[NV][idx];
-  r.c = srec[NV + 1][idx];
-  r.iw = srec[NV + 2][idx];
-}
 
-// Stencil accessor over the LDS plane.
+// Stencil accessor over the LDS plane: six cells at p + m * stride, p a
+// 32-bit LDS address (every value's offset from it folds into the LDS
+// instruction).
+typedef const __attribute__((address_space(3))) double lds_double;
 template <int NV>
-struct LdsSrc {  // six cells of the LDS plane at base + m*stride
-  double (*srec)[FP_N];
-  int base, stride;
+struct LdsSrc {
+  const lds_double* p;
+  int stride;
   __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
-    lds_get<NV>(srec, base + m * stride, r);
+    const lds_double* q = p + m * stride;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r.U[v] = q[v * FP_X];
+    r.p = q[NV * FP_X];
+    r.c = q[(NV + 1) * FP_X];
+    r.iw = q[(NV + 2) * FP_X];
   }
 };
+
+// The LDS address of srec[idx], opaque to the compiler so that it is not
+// split into a register part and a constant too large for an instruction
+// offset.
+__device__ __forceinline__ const lds_double* lds_addr(const double* srec, int idx) {
+  const lds_double* p = (const lds_double*)(srec + idx);
+  asm volatile("" : "+v"(p));
+  return p;
+}
 
 // Column of cells at fixed (x, y): element offset of its (x, y) position
 // after the boundary mapping, and the momentum signs of mirror ghosts.
@@ -146,7 +161,7 @@ struct ZSrc {
 template <int OUT, int WPE, int SPLIT, int HYB>
 __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
-  __shared__ double srec[NV + 3][FP_N];      // plane z with halo
+  __shared__ double srec[FP_Y * FP_ROW];     // plane z with halo (row, value, column)
   __shared__ double sfx[NV][NXF];            // x-face fluxes of plane z
   __shared__ double sfy[NV][NYF];            // y-face fluxes of plane z
   __shared__ double swin[2][NV + 3][FT_OWN]; // two oldest cells of each z window
@@ -179,7 +194,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   const int ox = t % FT_X, oy = t / FT_X;
   const int gx = x0 + ox, gy = y0 + oy;
   const bool valid = owner && gx < g.n[0] && gy < g.n[1];
-  const int lds_own = (oy + 3) * FP_X + (ox + 3);
+  const int lds_own = (oy + 3) * FP_ROW + (ox + 3);
   const Col ocol = make_col(g, gx, gy);
   const long long oout = (long long)gx + (long long)gy * g.stride[1];
 
@@ -195,7 +210,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     const int k = h / FT_X;
     hr = k < 3 ? k - 3 : FT_Y + k - 3;
   }
-  const int lds_halo = (hr + 3) * FP_X + (hc + 3);
+  const int lds_halo = (hr + 3) * FP_ROW + (hc + 3);
   const Col hcol = make_col(g, x0 + hc, y0 + hr);
 
   // owner registers: r0..r3 = cells z-1 .. z+2 at the top of iteration z;
@@ -290,8 +305,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     // x faces: thread t < 255 -> row t/17, face fx = t%17 at x0 + fx - 1/2
     if (t < NXF) {
       const int row = t / (FT_X + 1), fx = t % (FT_X + 1);
-      const int base = (row + 3) * FP_X + fx;
-      const LdsSrc<NV> src{srec, base, 1};
+      const LdsSrc<NV> src{lds_addr(srec, (row + 3) * FP_ROW + fx), 1};
       double F[NV];
       sgx[t] = face_linear_l<NV, 0, SPLIT, HYB>(src, ph, ph.eps_thr[0], lfx, F) != 0u;
 #pragma unroll
@@ -301,8 +315,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     // y faces: thread t -> column t%16, face fy = t/16 at y0 + fy - 1/2
     {
       const int col = t % FT_X, fy = t / FT_X;
-      const int base = fy * FP_X + col + 3;
-      const LdsSrc<NV> src{srec, base, FP_X};
+      const LdsSrc<NV> src{lds_addr(srec, fy * FP_ROW + col + 3), FP_ROW};
       double F[NV];
       sgy[t] = face_linear_l<NV, 1, SPLIT, HYB>(src, ph, ph.eps_thr[1], lfy, F) != 0u;
 #pragma unroll
