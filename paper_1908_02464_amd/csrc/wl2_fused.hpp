@@ -54,21 +54,60 @@ struct FusedArgs {
                              // into cfl->smax / status (next step's dt)
 };
 
+typedef __attribute__((address_space(3))) double lds_wdouble;
+typedef const __attribute__((address_space(3))) double lds_double;
+
+// The LDS address of p, opaque to the compiler so that it is not split into
+// a register part and a constant too large for an instruction offset (the
+// offsets of the values around it then fold into the LDS instructions).
+__device__ __forceinline__ lds_wdouble* lds_addr(double* p) {
+  lds_wdouble* q = (lds_wdouble*)p;
+  asm volatile("" : "+v"(q));
+  return q;
+}
+
 template <int NV>
 __device__ __forceinline__ void lds_put(double* srec, int idx, const LRec<NV>& r) {
   static_assert(NV + 3 == 8, "eight values per LDS cell");
+  lds_wdouble* q = lds_addr(srec + idx);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) srec[idx + v * FP_X] = r.U[v];
-  srec[idx + NV * FP_X] = r.p;
-  srec[idx + (NV + 1) * FP_X] = r.c;
-  srec[idx + (NV + 2) * FP_X] = r.iw;
+  for (int v = 0; v < NV; ++v) q[v * FP_X] = r.U[v];
+  q[NV * FP_X] = r.p;
+  q[(NV + 1) * FP_X] = r.c;
+  q[(NV + 2) * FP_X] = r.iw;
 }
 
+// z-window ring of a column owner: the eight values of a record as four
+// pairs, each an aligned 16-byte LDS word per owner (one 128-bit access
+// per pair, consecutive owners at consecutive words).
+constexpr int RING_SLOT = 4 * FT_OWN;  // double2 words per ring slot
 
-// Stencil accessor over the LDS plane: six cells at p + m * stride, p a
-// 32-bit LDS address (every value's offset from it folds into the LDS
-// instruction).
-typedef const __attribute__((address_space(3))) double lds_double;
+template <int NV>
+__device__ __forceinline__ void ring_store(double2* swin, int slot, int t, const LRec<NV>& r) {
+  static_assert(NV == 5, "five conserved values: four pairs per record");
+  double2* q = swin + slot * RING_SLOT + t;
+  q[0] = make_double2(r.U[0], r.U[1]);
+  q[FT_OWN] = make_double2(r.U[2], r.U[3]);
+  q[2 * FT_OWN] = make_double2(r.U[4], r.p);
+  q[3 * FT_OWN] = make_double2(r.c, r.iw);
+}
+
+template <int NV>
+__device__ __forceinline__ void ring_load(const double2* swin, int slot, int t, LRec<NV>& r) {
+  const double2* q = swin + slot * RING_SLOT + t;
+  const double2 a = q[0], b = q[FT_OWN], c = q[2 * FT_OWN], d = q[3 * FT_OWN];
+  r.U[0] = a.x;
+  r.U[1] = a.y;
+  r.U[2] = b.x;
+  r.U[3] = b.y;
+  r.U[4] = c.x;
+  r.p = c.y;
+  r.c = d.x;
+  r.iw = d.y;
+}
+
+// Stencil accessor over the LDS plane: six cells at p + m * stride, p an
+// opaque LDS address (lds_addr).
 template <int NV>
 struct LdsSrc {
   const lds_double* p;
@@ -140,19 +179,12 @@ __device__ __forceinline__ void load_col(const double* __restrict__ U, const KGr
 // j .. j+3 from registers.
 template <int NV>
 struct ZSrc {
-  double (*swin)[NV + 3][FT_OWN];
+  const double2* swin;
   int slot0, slot1, col;
   const LRec<NV>&r0, &r1, &r2, &r3;
-  __device__ __forceinline__ void ring(int slot, LRec<NV>& r) const {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) r.U[v] = swin[slot][v][col];
-    r.p = swin[slot][NV][col];
-    r.c = swin[slot][NV + 1][col];
-    r.iw = swin[slot][NV + 2][col];
-  }
   __device__ __forceinline__ void get(int m, LRec<NV>& r) const {
-    if (m == 0) ring(slot0, r);
-    else if (m == 1) ring(slot1, r);
+    if (m == 0) ring_load<NV>(swin, slot0, col, r);
+    else if (m == 1) ring_load<NV>(swin, slot1, col, r);
     else r = m == 2 ? r0 : m == 3 ? r1 : m == 4 ? r2 : r3;
   }
 };
@@ -164,7 +196,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   __shared__ double srec[FP_Y * FP_ROW];     // plane z with halo (row, value, column)
   __shared__ double sfx[NV][NXF];            // x-face fluxes of plane z
   __shared__ double sfy[NV][NYF];            // y-face fluxes of plane z
-  __shared__ double swin[2][NV + 3][FT_OWN]; // two oldest cells of each z window
+  __shared__ double2 swin[2 * RING_SLOT];    // two oldest cells of each z window
   __shared__ unsigned char sgx[NXF], sgy[NYF];  // face needs the nonlinear flux
 
   double dt = 0.0;
@@ -239,17 +271,8 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     make_lrec<NV>(u, ph, r3);
     // ring: cells z0-3 and z0-2
     const int s3 = (z0 - 3) & 1, s2 = (z0 - 2) & 1;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      swin[s3][v][t] = c0.U[v];
-      swin[s2][v][t] = c1.U[v];
-    }
-    swin[s3][NV][t] = c0.p;
-    swin[s3][NV + 1][t] = c0.c;
-    swin[s3][NV + 2][t] = c0.iw;
-    swin[s2][NV][t] = c1.p;
-    swin[s2][NV + 1][t] = c1.c;
-    swin[s2][NV + 2][t] = c1.iw;
+    ring_store<NV>(swin, s3, t, c0);
+    ring_store<NV>(swin, s2, t, c1);
     // face z0 - 1/2 (cells z0-3 .. z0+2): window c0, c1, r0, r1, r2, r3
     const WinSrc<NV> src{c0, c1, r0, r1, r2, r3};
     zprev = face_linear_l<NV, 2, SPLIT, HYB>(src, ph, ph.eps_thr[2], lfz, Fzp) != 0u;
@@ -262,11 +285,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       // retire cell z-1 into the ring (overwrites cell z-3), then shift:
       // registers become cells z .. z+3
       const int sl = (z - 1) & 1;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) swin[sl][v][t] = r0.U[v];
-      swin[sl][NV][t] = r0.p;
-      swin[sl][NV + 1][t] = r0.c;
-      swin[sl][NV + 2][t] = r0.iw;
+      ring_store<NV>(swin, sl, t, r0);
       r0 = r1;
       r1 = r2;
       r2 = r3;
