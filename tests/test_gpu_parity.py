@@ -360,6 +360,44 @@ def test_advance_to_t_end(orc, capi):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,bc", [(1, 1), (2, 0), (3, 1), (63, 1), (64, 2), (1008, 1), (1024, 0),
+                                  (1025, 1)])
+def test_advance_1d_sizes(orc, capi, n, bc):
+    """1D advance() at the edges of the single-workgroup kernel (one to 1024
+    cells; items past the grid edge on every wavefront) and just past it
+    (1025 cells, the stage kernels): bit-identical to step-by-step launches,
+    and the oracle's steps to the 100-step bar."""
+    import torch
+    # random two-state problems on a few cells can expand to vacuum (the
+    # oracle stops there too): Sod states below 16 cells
+    left, right = w.SOD if n < 16 else w.random_two_state(np.random.default_rng(100 + n))
+    U, dx = w.riemann_1d(n, left, right)
+    steps = 8
+    po, pg = params_pair(orc, capi, (n, 1, 1), dx, bc=[bc, bc, 1, 1, 1, 1])
+    ctx = capi.Context(n, 1, 1, dx, G, pg)
+    A = to_dev(U)
+    for _ in range(steps):
+        ctx.step(A)
+    ctx.close()
+    ctx = capi.Context(n, 1, 1, dx, G, pg)
+    B = to_dev(U)
+    ctx.advance(B, steps, 1e300)
+    t, _, k = ctx.clock()
+    st = ctx.status()
+    ctx.close()
+    torch.cuda.synchronize()
+    a, b = to_host(A), to_host(B)
+    assert st == 0 and k == steps
+    assert np.array_equal(a, b)
+    Uo = U.copy()
+    for _ in range(steps):
+        _, sto = orc.step(Uo, dx, G, po)
+        assert sto == 0
+    err = z20(b, Uo)
+    say(f"    n={n} bc={bc}: z20 = {err:.3e}")
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("n", [128, 5000])
 def test_advance_stops_at_nonphysical(capi, n):
     """advance() on a state with a non-physical cell takes no step: the status
