@@ -174,8 +174,8 @@ def main():
                     help="also run one device copy of a state array (known bytes) for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the hot path runs on one MI355X and multi-GPU sharding is a design note.",
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the hot path "
+              "runs on one MI355X, and sharding across GPUs is described, not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
