@@ -533,3 +533,54 @@ def test_full_size_sampled(orc, capi, which):
     say(f"    one-step sampled z20={worst:.3e}")
     assert worst <= 1e-12
     ctx.close()
+
+
+def _advection_state(n, axis, dim, t=0.0):
+    """rho = 1 + 0.2 sin(pi (s - t)), velocity 1 along `axis` (0 x, 1 y, 2 z),
+    p = 1 on [-1, 1] along the axis; the other extents are 4 cells of the
+    same values.  Returns (U with shape [nvar, nz, ny, nx], dx, shape)."""
+    ext = [4] * dim
+    ext[axis] = n
+    shape = tuple(ext) + (1,) * (3 - dim)  # (nx, ny, nz)
+    dx = 2.0 / n
+    s = -1.0 + (np.arange(n) + 0.5) * dx
+    rho1 = 1.0 + 0.2 * np.sin(np.pi * (s - t))
+    nv = dim + 2
+    U = np.zeros((nv, shape[2], shape[1], shape[0]))
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    rho = np.broadcast_to(rho1.reshape(bshape), U.shape[1:])
+    U[0] = rho
+    U[1 + axis] = rho
+    U[nv - 1] = 1.0 / (G - 1.0) + 0.5 * rho
+    return U, dx, shape
+
+
+@pytest.mark.parametrize("axis,dim", [(0, 1), (0, 2), (1, 2), (2, 3)])
+@pytest.mark.parametrize("hybrid,min_rate", [(0, 4.6), (2, 4.5)])
+def test_gpu_design_order_smooth_advection(capi, axis, dim, hybrid, min_rate):
+    """The GPU path's own convergence on smooth periodic advection along
+    each axis of 1D, 2D and 3D grids (the row kernel in x and y, the fused
+    3D kernel in z): errors against the exact translated profile after one
+    period, dt ~ dx^(5/3).  Fifth order for the hybrid scheme (every face
+    linear here) and for pure WENO-L2IS too: its regularised weights keep the
+    optimal order on smooth data (measured rates 4.92-5.00 from N = 32)."""
+    import torch
+    errs = []
+    for n in (32, 64, 128, 256):
+        U, dx, shape = _advection_state(n, axis, dim)
+        p = capi.params_default(*shape, dx, bc=[0] * 6, hybrid=hybrid)
+        ctx = capi.Context(*shape, dx, G, p)
+        Ud = to_dev(U)
+        dt0 = 0.5 * (2.0 / 32) / (1.0 + np.sqrt(G))
+        steps = int(np.ceil(2.0 / (dt0 * (32.0 / n) ** (5.0 / 3.0)) - 1e-9))
+        for _ in range(steps):
+            ctx.step(Ud, 2.0 / steps)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        ctx.close()
+        ex, _, _ = _advection_state(n, axis, dim, t=2.0)
+        errs.append(float(np.mean(np.abs(to_host(Ud).reshape(U.shape)[0] - ex[0]))))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    say(f"    axis={axis} dim={dim} hybrid={hybrid}: L1 errors {errs}, rates {rates}")
+    assert rates[-1] > min_rate and rates[-2] > min_rate, (errs, rates)
