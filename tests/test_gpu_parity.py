@@ -563,8 +563,8 @@ def test_gpu_design_order_smooth_advection(capi, axis, dim, hybrid, min_rate):
     each axis of 1D, 2D and 3D grids (the row kernel in x and y, the fused
     3D kernel in z): errors against the exact translated profile after one
     period, dt ~ dx^(5/3).  Fifth order for the hybrid scheme (every face
-    linear here) and for pure WENO-L2IS too: its regularised weights keep the
-    optimal order on smooth data (measured rates 4.92-5.00 from N = 32)."""
+    linear here) and for pure WENO-L2IS too (fifth order stated for the
+    regularised weights in Sec. 3.1; measured rates 4.92-5.00 from N = 32)."""
     import torch
     errs = []
     for n in (32, 64, 128, 256):

@@ -89,7 +89,12 @@ def _advect(orc, n, t_end, hybrid, dt=None):
     return U
 
 
-@pytest.mark.parametrize("hybrid,min_rate", [(0, 4.6), (2, 3.0)])
+# Pure WENO-L2IS converges at fifth order on the smooth profile (the paper
+# states fifth order for the regularised weights, Sec. 3.1); measured
+# 4.92 / 4.98 / 5.00 for N = 32..256, and still fifth order with lambda made
+# 1e12 times larger.  A mistake that shifts weight to the low-order 2-point
+# candidates or breaks a candidate reconstruction drops below 4.5.
+@pytest.mark.parametrize("hybrid,min_rate", [(0, 4.6), (2, 4.5)])
 def test_design_order_smooth_advection(orc, hybrid, min_rate):
     ns = [32, 64, 128, 256]
     errs = []
