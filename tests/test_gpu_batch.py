@@ -297,3 +297,60 @@ def test_fused_zchunk_bitwise_and_autotuner(capi):
     zc, wpe, times = autotune.tune_fused(32, 32, 32, dx, to_dev(U), steps=2, zchunks=(0, 8, 32),
                                          verbose=True)
     assert (zc, wpe) in times and len(times) == 6
+
+
+def test_batch_scheme_variants_and_boundaries(orc, capi):
+    """One batch holding runs with different schemes and boundaries (Roe
+    splitting, per-face switch, WENO only, linear only on smooth data, where
+    it stays physical; periodic and reflective walls): each run equals, bit for bit, its single-grid run
+    with the same parameters, and the oracle advanced to the same end time
+    within 1e-10."""
+    import torch
+    U1, dx1 = w.sod(150)
+    U2, dx2 = w.smooth_advection(96)
+    left, right = w.random_two_state(np.random.default_rng(8))
+    U3, dx3 = w.riemann_1d(120, left, right)
+    U4, dx4, _ = w.four_quadrant_2d(50, 44, 23)
+    U5, dx5, _ = w.four_quadrant_2d(33, 70, 24)
+    runs = [("sod_roe", U1, dx1, 0.08, dict(split=capi.SPLIT_ROE)),
+            ("adv_periodic_weno", U2, dx2, 0.2, dict(bc=[0, 0, 1, 1, 1, 1], hybrid=2)),
+            ("two_state_reflective_face", U3, dx3, 0.05, dict(bc=[2, 2, 1, 1, 1, 1], hybrid=1)),
+            ("adv_periodic_linear", U2, dx2, 0.2, dict(bc=[0, 0, 1, 1, 1, 1], hybrid=3)),
+            ("quad_face_mixed_bc", U4, dx4, 0.03, dict(bc=[0, 0, 2, 2, 1, 1], hybrid=1)),
+            ("quad_roe_reflective", U5, dx5, 0.04, dict(bc=[2, 1, 1, 2, 1, 1], split=capi.SPLIT_ROE))]
+    eng = capi.Batch(128 * MiB, 16)
+    slots = {}
+    for name, U, dx, te, kw in runs:
+        nx, ny, nz = _shape(U)
+        slots[eng.admit(U, nx, ny, nz, dx, te, params=capi.params_default(nx, ny, nz, dx, **kw))] = name
+    res = {}
+    for _ in range(10000):
+        if len(res) == len(runs):
+            break
+        eng.advance(8)
+        eng.stream.synchronize()
+        for s in eng.poll():
+            res[slots[s]] = eng.fetch(s)
+    eng.close()
+    assert len(res) == len(runs)
+    for name, U, dx, te, kw in runs:
+        nx, ny, nz = _shape(U)
+        Ub, tb, sb = res[name]
+        assert sb == 0 and tb == te, name
+        po, pg = params_pair(orc, capi, (nx, ny, nz), dx, **kw)
+        ctx = capi.Context(nx, ny, nz, dx, G, pg)
+        Ud = to_dev(U)
+        ctx.set_time(0.0)
+        while ctx.time()[0] < te:
+            ctx.advance(Ud, 64, te)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        Uc = to_host(Ud).reshape(Ub.shape)
+        ctx.close()
+        assert np.array_equal(Uc, Ub), name
+        Uo = U.copy()
+        t, n, st = orc.run(Uo, dx, G, po, te)
+        err = z20(Ub.reshape(Uo.shape), Uo)
+        say(f"    {name}: steps={n} z20={err:.3e}")
+        assert st == 0 and t == te
+        assert err <= 1e-10, name
