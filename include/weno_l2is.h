@@ -86,7 +86,10 @@ int weno_l2is_params_default(weno_l2is_params *p, int nx, int ny, int nz,
 
 /* Create a solver context for one grid.  hip_stream: hipStream_t (NULL =
  * the null stream); all of the context's work is enqueued there.  Allocates
- * the two RK stage buffers, one accumulator and a small control block. */
+ * the two RK stage buffers, one accumulator (per-direction path), the
+ * correction list (8 bytes per cell), a 4.4 KB control block and, for 2D
+ * grids of 131072 cells or more, the face-once correction buffers (68 bytes
+ * per cell).  About 2.2 GB for a 256^3 grid. */
 int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma,
                      const weno_l2is_params *p, void *hip_stream,
                      weno_l2is_ctx **out);
@@ -138,7 +141,10 @@ int weno_l2is_time(weno_l2is_ctx *ctx, double *t_host, double *last_dt_host,
 
 /* Per-face switch flags (1 = linear flux) and detector values sigma^s of
  * Eq.(30) along direction dir, computed by the same device code as the
- * sweeps.  Layout [nvar][..] with n_dir + 1 faces along dir (face f lies
+ * sweeps (the fused kernels evaluate the detector in another operation
+ * order, a few ulp apart, so a flag can differ only where sigma^s lies
+ * within that of the threshold).  Layout [nvar][..] with n_dir + 1 faces
+ * along dir (face f lies
  * between cells f-1 and f), the other extents unchanged, x fastest; both
  * are DEVICE pointers.  Asynchronous. */
 int weno_l2is_face_debug(weno_l2is_ctx *ctx, const double *U, int dir,
