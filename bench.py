@@ -106,19 +106,24 @@ def variants_3d(torch, capi, U0, dx, steps=10):
 
 def other_configs(torch, capi, workloads):
     """The 1D and 2D workloads run to their end: Sod 200 to t = 0.2,
-    Shu-Osher 1600 to t = 1.8 (transmissive), 2D four-quadrant 1024^2 for 200
-    steps.  Each through weno_l2is_advance on the fused 1D/2D kernel, timed
-    with events on the library's stream after one untimed warm-up run."""
+    Shu-Osher 1600 to t = 1.8 (transmissive), the interacting blast waves on
+    400 cells to t = 0.038 (reflective walls, Roe splitting), 2D
+    four-quadrant 1024^2 for 200 steps.  Each through weno_l2is_advance on
+    the fused 1D/2D kernel, timed with events on the library's stream after
+    one untimed warm-up run."""
     out = {}
     cases = []
     U, dx = workloads.sod(200)
-    cases.append(("sod200_t0.2", U, dx, (200, 1, 1), 0.2, None))
+    cases.append(("sod200_t0.2", U, dx, (200, 1, 1), 0.2, None, {}))
     U, dx = workloads.shu_osher(1600)
-    cases.append(("shu_osher1600_t1.8", U, dx, (1600, 1, 1), 1.8, None))
+    cases.append(("shu_osher1600_t1.8", U, dx, (1600, 1, 1), 1.8, None, {}))
+    U, dx = workloads.blast_waves(400)
+    cases.append(("blast_waves400_t0.038", U, dx, (400, 1, 1), 0.038, None,
+                  {"split": 2, "bc": [2, 2, 1, 1, 1, 1]}))
     U, dx, _ = workloads.four_quadrant_2d(1024, 1024, 2024)
-    cases.append(("quad2d_1024x1024_200steps", U, dx, (1024, 1024, 1), 1e300, 200))
-    for name, U0, dx, shape, t_end, nsteps in cases:
-        ctx = capi.Context(*shape, dx, GAMMA)
+    cases.append(("quad2d_1024x1024_200steps", U, dx, (1024, 1024, 1), 1e300, 200, {}))
+    for name, U0, dx, shape, t_end, nsteps, kw in cases:
+        ctx = capi.Context(*shape, dx, GAMMA, capi.params_default(*shape, dx, **kw))
         ncell = shape[0] * shape[1] * shape[2]
         res = None
         for rep in range(2):  # warm-up run, then the timed one

@@ -54,6 +54,15 @@ def sod(n=200):
     return riemann_1d(n, *SOD)
 
 
+def blast_waves(n=400, gamma=GAMMA):
+    """Two interacting blast waves on [0,1] (Sec. 4.3): rho = 1, u = 0 and
+    p = 1000 / 0.01 / 100 on [0, 0.1) / [0.1, 0.9) / [0.9, 1]; reflective
+    walls at both ends, Roe-speed splitting, t_end = 0.038."""
+    x, dx = centres(n, 0.0, 1.0)
+    p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+    return conserved(np.ones(n), [np.zeros(n)], p, gamma).reshape(3, 1, 1, n), dx
+
+
 def shu_osher(n=1600, gamma=GAMMA):
     """Mach-3 shock / entropy wave on [-5,5]: shocked state for x < -4."""
     x, dx = centres(n, -5.0, 5.0)

@@ -360,6 +360,41 @@ def test_advance_to_t_end(orc, capi):
     ctx.close()
 
 
+@pytest.mark.parametrize("split", [2, 0])
+def test_blast_waves_full_run(orc, capi, split):
+    """Interacting blast waves (Sec. 4.3: 400 cells, reflective walls, Roe
+    splitting as in the paper, and LLF) advanced on the device clock to
+    t = 0.038: the same number of steps as the oracle and its state to the
+    100-step bar.  Perturbing the oracle's state by one ulp after every step
+    moves its final state by 4e-13 of the grid maximum, so the bar leaves
+    room for the device's rounding over the ~1260 steps.  Mass and energy
+    stay conserved at the walls."""
+    import torch
+    say(f"[blast] 400 cells split={split} to t=0.038")
+    U, dx = w.blast_waves(400)
+    po, pg = params_pair(orc, capi, (400, 1, 1), dx, split=split, bc=[2, 2, 1, 1, 1, 1])
+    Uo = U.copy()
+    t, n, st = orc.run(Uo, dx, G, po, 0.038)
+    assert st == 0 and t == 0.038
+    ctx = capi.Context(400, 1, 1, dx, G, pg)
+    Ud = to_dev(U)
+    ctx.set_time(0.0)
+    ctx.advance(Ud, n + 10, 0.038)
+    tg, _, k = ctx.clock()
+    stg = ctx.status()
+    ctx.close()
+    torch.cuda.synchronize()
+    got = to_host(Ud).reshape(U.shape)
+    err = z20(got, Uo)
+    say(f"    steps oracle={n} gpu={k} z20={err:.3e}")
+    assert stg == 0 and tg == 0.038 and k == n
+    assert np.isfinite(got).all()
+    assert err <= 1e-10
+    m0, m1 = U.sum(axis=(1, 2, 3)), got.sum(axis=(1, 2, 3))
+    assert abs(m1[0] - m0[0]) <= 1e-12 * m0[0]
+    assert abs(m1[2] - m0[2]) <= 1e-12 * m0[2]
+
+
 @pytest.mark.parametrize("n,bc", [(1, 1), (2, 0), (3, 1), (63, 1), (64, 2), (1008, 1), (1024, 0),
                                   (1025, 1)])
 def test_advance_1d_sizes(orc, capi, n, bc):
