@@ -12,7 +12,10 @@
 // exchanged through LDS so that every cell receives its six face fluxes from
 // exactly one owner, in a fixed order (the result is deterministic).
 // Physical fluxes along the face direction are formed on the fly from the
-// light record.  The WENO branch of a flagged face is taken in place.
+// light record.  Every face takes the linear branch here; a cell next to a
+// face whose detector asks for the nonlinear flux is appended (with its
+// face mask) to a correction list, and weno_fix3d_kernel adds the
+// difference of the WENO-L2IS flux afterwards.
 // Tiles are numbered so that the workgroups resident on one XCD (dispatch is
 // round-robin over the 8 XCDs) take a contiguous range of tiles and share
 // their halos in that XCD's L2.

@@ -12,8 +12,8 @@ With --valu DIR (a run with the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64,
 SQ_INSTS_VALU and SQ_WAVES counters) the FP64 operations per dispatch are
 added: 64 lanes x (2 FMA + ADD + MUL + TRANS) wave instructions, i.e. every
 lane counted (inactive lanes of a partial wave included).
-The summary records a hash of the kernel sources so that stale counter
-numbers are recognised.
+The summary records a hash of the kernel sources (their code without
+comments) so that stale counter numbers are recognised.
 """
 from __future__ import annotations
 
@@ -23,6 +23,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -34,13 +35,26 @@ FUSED_FILES = ("wl2_device.hpp", "wl2_lface.hpp", "wl2_fused.hpp", "wl2_fused_la
                "wl2_fused3d.hip")
 
 
+_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/|\s+', re.S)
+
+
+def code_text(src: str) -> str:
+    """C++ source without its comments, runs of white space as one blank
+    (string and character literals kept as written): what the compiler
+    sees, so that a comment edit does not mark a profile stale."""
+    def keep(m):
+        t = m.group(0)
+        return t if t[0] in "\"'" else "\0"
+    return re.sub("\0+", " ", _TOKENS.sub(keep, src)).strip()
+
+
 def source_hash(files=FUSED_FILES, unit="wl2_fused3d.hip") -> str:
     from .build import compile_flags
     h = hashlib.sha256()
     for name in files:
-        with open(os.path.join(PKG, "csrc", name), "rb") as fh:
+        with open(os.path.join(PKG, "csrc", name), encoding="utf-8") as fh:
             h.update(name.encode())
-            h.update(fh.read())
+            h.update(code_text(fh.read()).encode())
     h.update(" ".join(compile_flags(unit)).encode())
     return h.hexdigest()[:16]
 

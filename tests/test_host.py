@@ -214,9 +214,14 @@ def test_rocprof_summary_parses_trace_and_scales_counters(tmp_path):
         wr.writerow(["__amd_rocclr_copyBuffer", "FETCH_SIZE", rs.COPY_KIB / 2.0, 1 << 20])
     vals, cal = rs.counter(str(cn), "wl2::k<2>", "FETCH_SIZE")
     assert vals == [100.0, 300.0] and cal == [rs.COPY_KIB / 2.0]
-    # the summary's source hash changes with the kernel sources' text
+    # the summary's source hash follows the kernel code, not its comments
     h = rs.source_hash()
     assert len(h) == 16 and h == rs.source_hash()
+    a = 'int a; // note "x"\n/* two\n lines */ const char* s = "a // b"; char c = \'"\';\nf("" : "+v"(q));'
+    b = 'int a;   // other\n// words\n const char* s = "a // b"; char c = \'"\'; f(""  :  "+v"(q));'
+    assert rs.code_text(a) == rs.code_text(b)
+    assert rs.code_text(a) == 'int a; const char* s = "a // b"; char c = \'"\'; f("" : "+v"(q));'
+    assert rs.code_text(a.replace("int a", "int z")) != rs.code_text(a)
 
 
 # ----------------------------------------------------------- build and bench
