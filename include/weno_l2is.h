@@ -97,11 +97,11 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma,
 /* Right-hand side of Eq.(19): dUdt = -sum_d (F_{j+1/2} - F_{j-1/2})_d / dx,
  * for the state U (device).  Stateless form: enqueued on the null stream,
  * asynchronous; an internal context per shape is cached and reused.
- * U and dUdt must not overlap. */
+ * U and dUdt must not overlap (WL2_E_PARAM if they share a byte). */
 int weno_l2is_rhs(const double *U, int nx, int ny, int nz, double dx,
                   double gamma, const weno_l2is_params *params, double *dUdt);
 
-/* The same on a context (its stream and scratch). */
+/* The same on a context (its stream and scratch); the same overlap rule. */
 int weno_l2is_rhs_ctx(weno_l2is_ctx *ctx, const double *U, double *dUdt);
 
 /* One SSP-RK3 step of U in place (Shu-Osher form:
@@ -146,7 +146,8 @@ int weno_l2is_time(weno_l2is_ctx *ctx, double *t_host, double *last_dt_host,
  * within that of the threshold).  Layout [nvar][..] with n_dir + 1 faces
  * along dir (face f lies
  * between cells f-1 and f), the other extents unchanged, x fastest; both
- * are DEVICE pointers.  Asynchronous. */
+ * are DEVICE pointers and may not overlap U or each other (WL2_E_PARAM).
+ * Asynchronous. */
 int weno_l2is_face_debug(weno_l2is_ctx *ctx, const double *U, int dir,
                          unsigned char *flags, double *sigma);
 
@@ -231,7 +232,9 @@ int weno_l2is_batch_poll(weno_l2is_batch *b, int *done_slots, int cap,
 
 /* Synchronize, copy the run's state to U_out (host if out_on_host, else
  * device), report its time, status bits and number of steps taken (t_out,
- * status, steps may be NULL), and free the slot and its memory.  Returns WL2_E_SLOT for a slot not in use. */
+ * status, steps may be NULL), and free the slot and its memory.  A run that
+ * has not reached t_end is cancelled where it stands.  Returns WL2_E_SLOT
+ * for a slot not in use. */
 int weno_l2is_batch_fetch(weno_l2is_batch *b, int slot, double *U_out,
                           int out_on_host, double *t_out, unsigned *status,
                           unsigned *steps);

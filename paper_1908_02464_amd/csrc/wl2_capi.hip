@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -90,6 +91,16 @@ const char* sweep_name() {
                                   {"sweep_y_write", "sweep_y_accum", "sweep_y_rk"},
                                   {"sweep_z_write", "sweep_z_accum", "sweep_z_rk"}};
   return tab[DIR][OUT];
+}
+
+// Do the byte ranges [a, a + na) and [b, b + nb) share a byte?
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+bool overlaps(const double* a, const double* b, size_t n) {
+  return overlaps(a, n * sizeof(double), b, n * sizeof(double));
 }
 
 int validate(int nx, int ny, int nz, double dx, double gamma, const weno_l2is_params* p) {
@@ -438,6 +449,7 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
 
 int weno_l2is_rhs_ctx(weno_l2is_ctx* c, const double* U, double* dUdt) {
   if (!c || !U || !dUdt) return WL2_E_NULL;
+  if (overlaps(U, dUdt, (size_t)c->nvar * c->ncell)) return WL2_E_PARAM;
   return hip_err(rhs_into(c, U, dUdt));
 }
 
@@ -446,6 +458,8 @@ int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gam
   if (!U || !dUdt) return WL2_E_NULL;
   int rc = validate(nx, ny, nz, dx, gamma, params);
   if (rc) return rc;
+  const size_t nc = (size_t)nx * ny * nz;
+  if (overlaps(U, dUdt, (size_t)(2 + (ny > 1) + (nz > 1)) * nc)) return WL2_E_PARAM;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WL2_E_HIP;
   std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -541,6 +555,10 @@ int weno_l2is_face_debug(weno_l2is_ctx* c, const double* U, int dir, unsigned ch
   if (!c || !U || !flags || !sigma) return WL2_E_NULL;
   if (dir < 0 || dir >= c->dim) return WL2_E_PARAM;
   long long nface = c->ncell / c->n[dir] * (c->n[dir] + 1);
+  const size_t nout = (size_t)c->nvar * (size_t)nface, ubytes = sizeof(double) * c->nvar * (size_t)c->ncell;
+  if (overlaps(U, ubytes, flags, nout) || overlaps(U, ubytes, sigma, nout * sizeof(double)) ||
+      overlaps(flags, nout, sigma, nout * sizeof(double)))
+    return WL2_E_PARAM;
   const long long blocks = (nface + 255) / 256;
   if (blocks > 0x7fffffffLL) return WL2_E_SHAPE;
   const dim3 gr((unsigned)blocks), bl(256);

@@ -108,6 +108,43 @@ def test_batch_mix_equals_alone_and_single_grid(capi):
         assert np.array_equal(Uc, Um), name
 
 
+def test_batch_cancel_mid_run(capi):
+    """Fetching a run before its t_end cancels it where it stands: its state
+    and clock after k steps equal k steps of a single-grid context, and the
+    run left in the batch finishes with the bits of running it alone."""
+    import torch
+    items = _mix()
+    sod = next(it for it in items if it[0] == "sod200")
+    quad = next(it for it in items if it[0] == "quad48x40")
+    eng = capi.Batch(256 * MiB, 8)
+    s_sod = eng.admit(sod[1], 200, 1, 1, sod[2], sod[3])
+    s_quad = eng.admit(quad[1], 48, 40, 1, quad[2], quad[3])
+    eng.advance(10)
+    eng.stream.synchronize()
+    Uc, tc, stc, kc = eng.fetch(s_sod, with_steps=True)
+    assert stc == 0 and kc == 10 and 0.0 < tc < sod[3]
+    ctx = capi.Context(200, 1, 1, sod[2])
+    Ud = to_dev(sod[1])
+    ctx.set_time(0.0)
+    ctx.advance(Ud, 10, sod[3])
+    t1, _, k1 = ctx.clock()
+    torch.cuda.synchronize()
+    assert k1 == 10 and t1 == tc
+    assert np.array_equal(to_host(Ud).reshape(Uc.shape), Uc)
+    ctx.close()
+    res = None
+    for _ in range(1000):
+        eng.advance(16)
+        eng.stream.synchronize()
+        if s_quad in eng.poll():
+            res = eng.fetch(s_quad)
+            break
+    eng.close()
+    assert res is not None and res[1] == quad[3] and res[2] == 0
+    alone = _run_batch(capi, [quad])["quad48x40"]
+    assert np.array_equal(res[0], alone[0])
+
+
 def test_batch_vs_oracle(orc, capi):
     items = _mix()
     res = _run_batch(capi, items)

@@ -482,6 +482,26 @@ def test_invalid_arguments(capi):
     p2 = capi.params_default(2, 1, 1, 0.1, bc=[2, 2, 1, 1, 1, 1])
     with pytest.raises(capi.WenoL2ISError):
         capi.Context(2, 1, 1, 0.1, 1.4, p2)  # reflective needs 3 cells
+    # dU/dt may not overlap U (refused before anything is enqueued)
+    buf = torch.ones(3 * 8 + 1, dtype=torch.float64, device="cuda")
+    p3 = capi.params_default(8, 1, 1, 0.1)
+    ctx = capi.Context(8, 1, 1, 0.1, 1.4, p3)
+    for out in (buf[:24], buf[1:25]):
+        with pytest.raises(capi.WenoL2ISError):
+            capi.rhs(buf[:24], 8, 1, 1, 0.1, 1.4, p3, out)
+        with pytest.raises(capi.WenoL2ISError):
+            ctx.rhs(buf[:24], out)
+    sig = torch.empty(27, dtype=torch.float64, device="cuda")  # 3 fields x 9 faces
+    fl = torch.empty(27, dtype=torch.uint8, device="cuda")
+    big = torch.ones(27, dtype=torch.float64, device="cuda")
+    with pytest.raises(capi.WenoL2ISError):
+        ctx.face_debug(big[:24], 0, fl, big)  # sigma over U
+    ctx.face_debug(buf[:24], 0, fl, sig)
+    dU = torch.empty(24, dtype=torch.float64, device="cuda")
+    ctx.rhs(buf[:24], dU)  # disjoint arrays are accepted
+    torch.cuda.synchronize()
+    assert torch.all(dU == 0.0)  # uniform state
+    ctx.close()
 
 
 def _sample_cells(shape, n, rng):
