@@ -6,6 +6,9 @@ suite, ``__graft_entry__.smoke`` and the CPU-baseline leg of ``bench.py`` may
 import this module.  It never serves as a fallback for the GPU library.
 
 Arrays are numpy float64, layout [nvar][nz][ny][nx] (x fastest).
+The environment variable ORACLE_L2IS_LIB names another build of the same
+sources to load instead (the planted-mistake test loads altered copies of
+the oracle this way; the files here are never altered).
 """
 from __future__ import annotations
 
@@ -16,7 +19,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle_l2is.so")
+DEFAULT_LIB = os.path.join(HERE, "liboracle_l2is.so")  # what build() writes
+LIB_PATH = os.environ.get("ORACLE_L2IS_LIB") or DEFAULT_LIB  # what lib() loads
 SOURCES = ["weno_scalar.c", "charsys.c", "face.c", "solver.c"]
 
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
@@ -24,15 +28,16 @@ SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+def build(verbose: bool = False, src_dir: str = HERE, out: str = DEFAULT_LIB) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction):
+    the sources in src_dir (default: these) into the library out."""
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", LIB_PATH]
-    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+           "-fno-fast-math", "-Wall", "-o", out]
+    cmd += [os.path.join(src_dir, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return LIB_PATH
+    return out
 
 
 class Params(C.Structure):
@@ -55,7 +60,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if LIB_PATH == DEFAULT_LIB and not os.path.exists(LIB_PATH):
             build()
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)

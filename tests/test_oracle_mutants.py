@@ -1,0 +1,83 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a temporary copy of the oracle's C sources
+(the files under oracle/ are not touched), builds it with the oracle's own
+flags, and runs the CPU pin suites against that build in a child process
+(ORACLE_L2IS_LIB).  Every planted mistake must make a pin fail.  The cases
+are the kinds of slip the method invites: an index of the mirrored f-
+stencil, a sign of the flux splitting, an L2 error term, a sign inside
+tau5, the Roe density of the detector, a coefficient of the six-point
+central flux, a Runge-Kutta weight, the mirror index of a reflective ghost,
+and weights of another WENO family (inverse-square smoothness weights),
+which lose the fifth order on smooth data.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+PINS = ["tests/test_oracle_scalar.py", "tests/test_oracle_face.py", "tests/test_oracle_solutions.py"]
+
+# (name, file, text as written, planted mistake)
+MUTANTS = [
+    ("mirrored_stencil_offset", "face.c",
+     "am[m] = fm[5 - m];", "am[m] = fm[4 - m];"),
+    ("split_sign", "face.c",
+     "fm[m] = 0.5 * (g[m] - alpha[s] * v[m]);", "fm[m] = 0.5 * (g[m] + alpha[s] * v[m]);"),
+    ("E1_dropped", "weno_scalar.c",
+     "E[1] = E[0];", "E[1] = 0.0;"),
+    ("tau5_sign", "weno_scalar.c",
+     "t2 = fp2 - 2.0 * fp1 + 2.0 * fm1 - fm2;", "t2 = fp2 - 2.0 * fp1 - 2.0 * fm1 - fm2;"),
+    ("roe_density_arithmetic_mean", "charsys.c",
+     "rhot = wl * wr;", "rhot = 0.5 * (pl[0] + pr[0]);"),
+    ("central_flux_tap", "face.c",
+     "37.0 * (F6[2][i] + F6[3][i])", "36.0 * (F6[2][i] + F6[3][i])"),
+    ("rk_stage2_weights", "solver.c",
+     "U2[k] = 0.75 * U[k] + 0.25 * (U1[k] + dt * Lk[k]);",
+     "U2[k] = 0.25 * U[k] + 0.75 * (U1[k] + dt * Lk[k]);"),
+    ("reflective_ghost_index", "solver.c",
+     "return -1 - k;", "return -k;"),
+    ("inverse_square_weights", "weno_scalar.c",
+     "alpha[k] = d[k] * (1.0 + lam * tau5 / (lam * beta[k] + E[k] + eps_w));",
+     "alpha[k] = d[k] / ((beta[k] + eps_w) * (beta[k] + eps_w));"),
+]
+
+
+# the unaltered sources through the same copy / build / load route: the pins
+# must pass, so a failure of a mutant is the planted mistake's doing
+CONTROL = ("control_unaltered", "face.c", "am[m] = fm[5 - m];", "am[m] = fm[5 - m];")
+
+
+def test_planted_mistakes_fail_a_pin(tmp_path):
+    from oracle import pyoracle
+    procs = []
+    for name, fname, old, new in [CONTROL] + MUTANTS:
+        d = tmp_path / name
+        d.mkdir()
+        for f in os.listdir(ORACLE):
+            if f.endswith((".c", ".h")):
+                shutil.copy(os.path.join(ORACLE, f), d / f)
+        src = (d / fname).read_text()
+        assert src.count(old) == 1, (name, "text not found once in " + fname)
+        (d / fname).write_text(src.replace(old, new))
+        lib = str(d / "liboracle_mutant.so")
+        pyoracle.build(src_dir=str(d), out=lib)
+        env = dict(os.environ, ORACLE_L2IS_LIB=lib, OMP_NUM_THREADS="1")
+        cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+               "-m", "not gpu", *PINS]
+        procs.append((name, subprocess.Popen(cmd, cwd=ROOT, env=env, stdout=subprocess.PIPE,
+                                             stderr=subprocess.STDOUT, text=True)))
+    survived = []
+    for name, p in procs:
+        out, _ = p.communicate(timeout=600)
+        if name == CONTROL[0]:
+            assert p.returncode == 0, out[-2000:]
+            continue
+        # exit code 1: tests ran and at least one failed
+        if p.returncode != 1 or "FAILED" not in out:
+            survived.append((name, p.returncode, out.strip().splitlines()[-1:]))
+    assert not survived, survived
