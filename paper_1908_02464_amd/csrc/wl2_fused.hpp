@@ -18,7 +18,10 @@
 // difference of the WENO-L2IS flux afterwards.
 // Tiles are numbered so that the workgroups resident on one XCD (dispatch is
 // round-robin over the 8 XCDs) take a contiguous range of tiles and share
-// their halos in that XCD's L2.
+// their halos in that XCD's L2.  A tile at the high x or y edge of the grid
+// (256 = 17 x 15 + 1 rows leaves a last tile row one cell high) computes
+// only the faces of its in-grid cells and loads only the records they read
+// (whole wavefronts then skip the work).
 #pragma once
 #include "wl2_fused_launch.hpp"
 #include "wl2_lface.hpp"
@@ -234,6 +237,9 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   const int ox = t % FT_X, oy = t / FT_X;
   const int gx = x0 + ox, gy = y0 + oy;
   const bool valid = owner && gx < g.n[0] && gy < g.n[1];
+  // extent of the tile inside the grid (smaller in the tiles at the high x
+  // and y edges): only the faces of in-grid cells are computed
+  const int cols_v = min(FT_X, g.n[0] - x0), rows_v = min(FT_Y, g.n[1] - y0);
   const int lds_own = (oy + 3) * FP_ROW + (ox + 3);
   const Col ocol = make_col(g, gx, gy);
   const long long oout = (long long)gx + (long long)gy * g.stride[1];
@@ -252,6 +258,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   }
   const int lds_halo = (hr + 3) * FP_ROW + (hc + 3);
   const Col hcol = make_col(g, x0 + hc, y0 + hr);
+  // records that a computed face reads: tile columns up to cols_v + 2 and
+  // rows up to rows_v + 2 (all of them except in the edge tiles)
+  const bool own_need = owner && ox < cols_v + 3 && oy < rows_v + 3;
+  const bool halo_need = t < NHALO && hc < cols_v + 3 && hr < rows_v + 3;
 
   // owner registers: r0..r3 = cells z-1 .. z+2 at the top of iteration z;
   // the ring holds cell c in slot (c & 1)
@@ -262,7 +272,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   double cfl_max = 0.0;  // CFL speed of the cells written here (a.cfl set)
   bool cfl_bad = false;
   double unp[NV] = {};  // U^n of cell z (RK stages 2, 3), loaded a phase ahead
-  if (owner) {
+  if (own_need) {
     double u[NV];
     LRec<NV> c0, c1;
     load_col<NV>(a.Uk, g, ocol, z0 - 3, u);
@@ -286,10 +296,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     zprev = face_linear_l<NV, 2, SPLIT, HYB>(src, ph, ph.eps_thr[2], lfz, Fzp) != 0u;
     load_col_raw<NV>(a.Uk, g, ocol, z0 + 3, upre);
   }
-  if (t < NHALO) load_col_raw<NV>(a.Uk, g, hcol, z0, hpre);
+  if (halo_need) load_col_raw<NV>(a.Uk, g, hcol, z0, hpre);
 
   for (int z = z0; z < z1; ++z) {
-    if (owner) {
+    if (own_need) {
       // retire cell z-1 into the ring (overwrites cell z-3), then shift:
       // registers become cells z .. z+3
       const int sl = (z - 1) & 1;
@@ -319,7 +329,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
         for (int v = 0; v < NV; ++v) unp[v] = __builtin_nontemporal_load(&a.Un[v * g.ncell + offn]);
       }
     }
-    if (t < NHALO) {
+    if (halo_need) {
       LRec<NV> hrec;
       col_flip<NV>(g, hcol, z, hpre);
       make_lrec<NV>(hpre, ph, hrec);
@@ -330,7 +340,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
     // x faces: thread t < 255 -> row t/17, face fx = t%17 at x0 + fx - 1/2
-    if (t < NXF) {
+    if (t < NXF && t / (FT_X + 1) < rows_v && t % (FT_X + 1) <= cols_v) {
       const int row = t / (FT_X + 1), fx = t % (FT_X + 1);
       const LdsSrc<NV> src{lds_addr(srec, (row + 3) * FP_ROW + fx), 1};
       double F[NV];
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     }
     __builtin_amdgcn_sched_barrier(0);
     // y faces: thread t -> column t%16, face fy = t/16 at y0 + fy - 1/2
-    {
+    if (t % FT_X < cols_v && t / FT_X <= rows_v) {
       const int col = t % FT_X, fy = t / FT_X;
       const LdsSrc<NV> src{lds_addr(srec, fy * FP_ROW + col + 3), FP_ROW};
       double F[NV];
@@ -350,7 +360,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     }
     __syncthreads();
     __builtin_amdgcn_sched_barrier(0);
-    if (owner) {
+    if (valid) {
       // z face z + 1/2: cells z-2, z-1 (ring), z .. z+3 (registers)
       double Fz[NV];
       const ZSrc<NV> src{swin, (z - 2) & 1, (z - 1) & 1, t, r0, r1, r2, r3};
