@@ -31,7 +31,6 @@ namespace wl2 {
 constexpr int FT_THREADS = 256;
 constexpr int FT_OWN = FT_X * FT_Y;              // 240 column owners
 constexpr int FP_X = FT_X + 6, FP_Y = FT_Y + 6;  // LDS plane pitch (with halo)
-constexpr int FP_N = FP_X * FP_Y;
 // LDS plane layout: row-major cells, the eight record values of a row
 // interleaved (row, value, column), so the 48 values of an x-face stencil
 // lie within the immediate-offset reach of one LDS address (a y-face
@@ -45,10 +44,6 @@ constexpr int FP_ROW = 8 * FP_X + 1;  // doubles per LDS row (NV + 3 = 8 values)
 constexpr int NXF = (FT_X + 1) * FT_Y;           // 255 x faces per plane
 constexpr int NYF = FT_X * (FT_Y + 1);           // 256 y faces per plane
 constexpr int NHALO = 6 * FT_Y + 6 * FT_X;       // 186 halo cells per plane
-
-struct V5 {
-  double v[5];
-};
 
 struct FusedArgs {
   const double* Uk;   // stage input

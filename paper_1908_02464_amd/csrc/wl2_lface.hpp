@@ -67,16 +67,6 @@ __device__ __forceinline__ void lflux(const LRec<NV>& r, double (&F)[NV], double
 }
 
 template <int NV, int DIR>
-__device__ __forceinline__ void to_cellrec(const LRec<NV>& r, CellRec<NV>& c) {
-#pragma unroll
-  for (int v = 0; v < NV; ++v) c.U[v] = r.U[v];
-  lflux<NV, DIR>(r, c.F, c.un);
-  c.c = r.c;
-  c.iw = r.iw;
-  c.p = r.p;
-}
-
-template <int NV, int DIR>
 __device__ __forceinline__ void roe_light(const LRec<NV>& L, const LRec<NV>& R, const KPhys& ph,
                                           Roe<NV>& s) {
   constexpr int DIM = NV - 2;
