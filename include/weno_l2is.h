@@ -87,9 +87,11 @@ int weno_l2is_params_default(weno_l2is_params *p, int nx, int ny, int nz,
 /* Create a solver context for one grid.  hip_stream: hipStream_t (NULL =
  * the null stream); all of the context's work is enqueued there.  Allocates
  * the two RK stage buffers, one accumulator (per-direction path), the
- * correction list (8 bytes per cell), a 4.4 KB control block and, for 2D
- * grids of 131072 cells or more, the face-once correction buffers (68 bytes
- * per cell).  About 2.2 GB for a 256^3 grid. */
+ * correction list (8 bytes per cell), a 4.4 KB control block, for 2D
+ * grids of 131072 cells or more the face-once correction buffers (68 bytes
+ * per cell), and for 3D grids with every face WENO (WL2_HYB_WENO_ONLY, LLF
+ * splitting) a face buffer (120 bytes per cell).  About 2.2 GB for a 256^3
+ * grid (4.2 GB with every face WENO). */
 int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma,
                      const weno_l2is_params *p, void *hip_stream,
                      weno_l2is_ctx **out);
@@ -162,7 +164,8 @@ int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
  * WL2_PATH_SWEEPS (one kernel per direction, partial sums through memory),
  * WL2_PATH_FUSED_CELLS (the fused stage kernel with the nonlinear
  * corrections computed per listed cell even where the default corrects
- * each flagged face once: 2D grids of 131072 cells or more).
+ * each flagged face once: 2D grids of 131072 cells or more, and 3D grids
+ * with every face WENO).
  * zchunk: z planes (3D) or rows (2D, at most 62) per work item of the fused
  * kernels (0 = automatic).  waves_per_simd: register budget of the 3D fused
  * kernel, 1 or 2 (0 = default 2).  The sweeps agree with the fused kernels

@@ -35,6 +35,7 @@ struct weno_l2is_ctx {
   unsigned long long* list;  // cells next to faces needing the WENO flux (fused kernels)
   double* fo_D = nullptr;          // 2D face-once corrections: face changes per list entry
   unsigned int* fo_map = nullptr;  // and the cell -> list entry map (null: per-cell kernel)
+  double* fo3 = nullptr;           // 3D, every face WENO: each face's change (face-once)
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
@@ -300,10 +301,8 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
   L.rk_b = rb;
   L.out_kind = out_kind;
   L.zc = fused_zchunk(c);
-  L.wpe = c->wpe;
-  // compile-time fast path for the paper's 1D/3D defaults: LLF splitting,
-  // per-field switch
-  L.fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
+  L.wpe = c->wpe;  // the scheme's build is chosen from L.ph
+  L.fo3 = c->path == WL2_PATH_FUSED_CELLS ? nullptr : c->fo3;
   for (int d = 0; d < 3; ++d) L.n[d] = c->n[d];
   L.g = c->g;
   L.ph = c->ph;
@@ -416,6 +415,10 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
          hipMalloc(&c->fo_map, sizeof(unsigned int) * (size_t)c->ncell) == hipSuccess &&
          // every map value stays a valid entry index (< ncell) from the start
          hipMemsetAsync(c->fo_map, 0, sizeof(unsigned int) * (size_t)c->ncell, c->stream) == hipSuccess;
+  // 3D with every face WENO (LLF splitting): the corrections compute each
+  // face once into a face buffer (15 doubles per cell)
+  if (ok && c->dim == 3 && p->hybrid == WL2_HYB_WENO_ONLY && p->split == WL2_SPLIT_LLF)
+    ok = hipMalloc(&c->fo3, sizeof(double) * fused3d_face_doubles(c->n)) == hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->U1);
@@ -424,6 +427,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
     (void)hipFree(c->list);
     (void)hipFree(c->fo_D);
     (void)hipFree(c->fo_map);
+    (void)hipFree(c->fo3);
     (void)hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
@@ -443,6 +447,7 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   (void)hipFree(c->list);
   (void)hipFree(c->fo_D);
   (void)hipFree(c->fo_map);
+  (void)hipFree(c->fo3);
   (void)hipFree(c->ctl);
   delete c;
 }

@@ -370,17 +370,21 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
              (sgy[iy + FT_X] ? 8u : 0u) | (zprev ? 16u : 0u) | (zcur ? 32u : 0u);
       }
       zprev = zcur;
-      // wave-aggregated append to the correction list
-      const unsigned long long ball = __ballot(cm != 0u);
-      if (ball) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((long long)ball) - 1;
-        unsigned int basei = 0;
-        if (lane == leader) basei = atomicAdd(a.list_n, (unsigned int)__popcll(ball));
-        basei = __shfl(basei, leader, 64);
-        if (cm) {
-          const unsigned int rank = __popcll(ball & ((1ull << lane) - 1ull));
-          a.list[basei + rank] = ((unsigned long long)off << 8) | cm;
+      // wave-aggregated append to the correction list (none when every
+      // face is WENO by construction: the correction kernel then walks all
+      // cells)
+      if (HYB != HYB_WENO_ONLY) {
+        const unsigned long long ball = __ballot(cm != 0u);
+        if (ball) {
+          const int lane = threadIdx.x & 63;
+          const int leader = __ffsll((long long)ball) - 1;
+          unsigned int basei = 0;
+          if (lane == leader) basei = atomicAdd(a.list_n, (unsigned int)__popcll(ball));
+          basei = __shfl(basei, leader, 64);
+          if (cm) {
+            const unsigned int rank = __popcll(ball & ((1ull << lane) - 1ull));
+            a.list[basei + rank] = ((unsigned long long)off << 8) | cm;
+          }
         }
       }
       if (valid) {
@@ -430,7 +434,12 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
     if (!(dt > 0.0)) return;
     scale = a.rk_b * dt;
   }
-  const unsigned int n = *a.list_n;
+  // every face WENO (compile-time): every in-grid cell has all six faces
+  // flagged, so the cells are walked in index order instead of a list (the
+  // same cells and masks a list would hold; each cell's result does not
+  // depend on the order)
+  constexpr bool dense = HYB == HYB_WENO_ONLY;
+  const unsigned int n = dense ? (unsigned int)g.ncell : *a.list_n;
   double cfl_max = 0.0;
   bool cfl_bad = false;
   const unsigned int threads = gridDim.x * blockDim.x;
@@ -441,7 +450,7 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
   const bool grouped = n <= threads / GRP;
   const unsigned int step = grouped ? threads / GRP : threads;
   for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step) {
-    const unsigned long long e = a.list[i];
+    const unsigned long long e = dense ? (((unsigned long long)i << 8) | 0x3full) : a.list[i];
     const long long off = (long long)(e >> 8);
     const unsigned cm = (unsigned)(e & 0xffu);
     const int x = (int)(off % g.n[0]);
@@ -461,6 +470,85 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
         const double m[3] = {un[1], un[2], un[3]};
         cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
       }
+    }
+  }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
+}
+
+// Every face WENO, face-once form: the change of each face's flux (WENO
+// minus linear) computed once, into D[v][face] with the faces of direction
+// DIR numbered x + ex * (y + ey * z), (ex, ey, ez) the grid extents with one
+// more face along DIR (face f lies between cells f-1 and f).  A face's change
+// depends on its position only, so it equals what the per-cell kernel
+// computes for either of its cells.
+template <int OUT, int DIR, int SPLIT, int HYB>
+__global__ __launch_bounds__(128) void weno_face3d_kernel(FusedArgs a, KGrid g, KPhys ph, double* D) {
+  constexpr int NV = 5;
+  if (OUT == OUT_RK && !(a.ctl->dt > 0.0)) return;
+  const long long ex = g.n[0] + (DIR == 0), ey = g.n[1] + (DIR == 1), ez = g.n[2] + (DIR == 2);
+  const long long nf = ex * ey * ez;
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += step) {
+    const int x = (int)(i % ex);
+    const int y = (int)((i / ex) % ey);
+    const int z = (int)(i / (ex * ey));
+    double dF[NV];
+    face_delta<NV, DIR, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[DIR], x, y, z, 0, dF);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) D[v * nf + i] = dF[v];
+  }
+}
+
+// Face-once form, per cell: the six face changes from D summed in the fixed
+// order x-, x+, y-, y+, z-, z+ (+ below, - above) and added to the output
+// exactly as weno_fix3d_kernel adds them (the same bits); the CFL speed of
+// the new state is folded for every cell; the next stage's list counter is
+// cleared.
+template <int OUT>
+__global__ __launch_bounds__(256) void weno_sum3d_kernel(FusedArgs a, KGrid g, KPhys ph,
+                                                         const double* Dx, const double* Dy,
+                                                         const double* Dz) {
+  constexpr int NV = 5;
+  if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
+  double scale = 1.0;
+  if (OUT == OUT_RK) {
+    const double dt = a.ctl->dt;
+    if (!(dt > 0.0)) return;
+    scale = a.rk_b * dt;
+  }
+  const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
+  double cfl_max = 0.0;
+  bool cfl_bad = false;
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < g.ncell; c += step) {
+    const long long x = c % nx, y = (c / nx) % ny, z = c / (nx * ny);
+    const long long fx = x + (nx + 1) * (y + ny * z);
+    const long long fy = x + nx * (y + (ny + 1) * z);
+    const long long fz = c;
+    const long long lo[3] = {fx, fy, fz}, hi[3] = {fx + 1, fy + nx, fz + nx * ny};
+    const double* Dd[3] = {Dx, Dy, Dz};
+    const long long nf[3] = {nfx, nfy, nfz};
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int dir = f >> 1;
+      const long long idx = (f & 1) ? hi[dir] : lo[dir];
+      const double sg = (f & 1) ? -1.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sg * Dd[dir][v * nf[dir] + idx];
+    }
+    double un[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      un[v] = a.out[v * g.ncell + c] + scale * (acc[v] * ph.inv_dx);
+      a.out[v * g.ncell + c] = un[v];
+    }
+    if (OUT == OUT_RK && a.cfl != nullptr) {
+      const double m[3] = {un[1], un[2], un[3]};
+      cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
     }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);

@@ -34,41 +34,93 @@ hipError_t fused3d_reset(const FusedLaunch& L) {
   return hipGetLastError();
 }
 
+// Compile-time scheme builds (the splitting and switch folded in, no
+// register spills) for the paper's default (LLF, per-field switch) and for
+// the schemes the benchmark and the robustness runs use: every face WENO,
+// every face linear, Roe-speed splitting.  Any other combination, and the
+// one-wave-per-SIMD budget of those, takes the build that reads the scheme
+// at run time.  The arithmetic is the same source either way.
 hipError_t fused3d_main(const FusedLaunch& L) {
   const FusedArgs a = make_args(L);
   const long long nzc = (L.n[2] + a.zc - 1) / a.zc;
   const long long blocks = (long long)a.tiles_x * a.tiles_y * nzc;
   if (a.zc < 1 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 gr((unsigned)blocks), bl(FT_THREADS);
+  const int sp = L.ph.split, hy = L.ph.hybrid;
+  const bool dflt = sp == SPLIT_LLF && hy == HYB_PER_FIELD;
 #define WL2_FUSED(O, W, S, H) \
   hipLaunchKernelGGL((fused3d_kernel<O, W, S, H>), gr, bl, 0, L.stream, a, L.g, L.ph)
-  if (L.out_kind == OUT_RK) {
-    if (L.wpe == 2) {
-      if (L.fast) WL2_FUSED(OUT_RK, 2, 0, 0); else WL2_FUSED(OUT_RK, 2, -1, -1);
-    } else {
-      if (L.fast) WL2_FUSED(OUT_RK, 1, 0, 0); else WL2_FUSED(OUT_RK, 1, -1, -1);
-    }
-  } else {
-    if (L.wpe == 2) {
-      if (L.fast) WL2_FUSED(OUT_WRITE, 2, 0, 0); else WL2_FUSED(OUT_WRITE, 2, -1, -1);
-    } else {
-      if (L.fast) WL2_FUSED(OUT_WRITE, 1, 0, 0); else WL2_FUSED(OUT_WRITE, 1, -1, -1);
-    }
-  }
+#define WL2_FUSED_SCHEMES(O)                                                         \
+  do {                                                                               \
+    if (L.wpe != 2) {                                                                \
+      if (dflt) WL2_FUSED(O, 1, SPLIT_LLF, HYB_PER_FIELD);                           \
+      else WL2_FUSED(O, 1, -1, -1);                                                  \
+    } else if (dflt) {                                                               \
+      WL2_FUSED(O, 2, SPLIT_LLF, HYB_PER_FIELD);                                     \
+    } else if (sp == SPLIT_LLF && hy == HYB_WENO_ONLY) {                             \
+      WL2_FUSED(O, 2, SPLIT_LLF, HYB_WENO_ONLY);                                     \
+    } else if (sp == SPLIT_LLF && hy == HYB_LINEAR_ONLY) {                           \
+      WL2_FUSED(O, 2, SPLIT_LLF, HYB_LINEAR_ONLY);                                   \
+    } else if (sp == SPLIT_ROE && hy == HYB_PER_FIELD) {                             \
+      WL2_FUSED(O, 2, SPLIT_ROE, HYB_PER_FIELD);                                     \
+    } else {                                                                         \
+      WL2_FUSED(O, 2, -1, -1);                                                       \
+    }                                                                                \
+  } while (0)
+  if (L.out_kind == OUT_RK) WL2_FUSED_SCHEMES(OUT_RK);
+  else WL2_FUSED_SCHEMES(OUT_WRITE);
+#undef WL2_FUSED_SCHEMES
 #undef WL2_FUSED
+  return hipGetLastError();
+}
+
+size_t fused3d_face_doubles(const int n[3]) {
+  const size_t nx = n[0], ny = n[1], nz = n[2];
+  return 5 * ((nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1));
+}
+
+// Every face WENO with a face buffer: each face's change once (three
+// launches, one per direction), then the per-cell sums.
+template <int O>
+static hipError_t fix_face_once(const FusedLaunch& L, const FusedArgs& a) {
+  const long long nx = L.n[0], ny = L.n[1], nz = L.n[2];
+  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
+  double* Dx = L.fo3;
+  double* Dy = Dx + 5 * nfx;
+  double* Dz = Dy + 5 * nfy;
+  const auto blocks = [](long long n, int t) {
+    const long long b = (n + t - 1) / t;
+    return dim3((unsigned)(b < (1ll << 20) ? b : (1ll << 20)));
+  };
+  hipLaunchKernelGGL((weno_face3d_kernel<O, 0, SPLIT_LLF, HYB_WENO_ONLY>), blocks(nfx, 128), dim3(128), 0,
+                     L.stream, a, L.g, L.ph, Dx);
+  hipLaunchKernelGGL((weno_face3d_kernel<O, 1, SPLIT_LLF, HYB_WENO_ONLY>), blocks(nfy, 128), dim3(128), 0,
+                     L.stream, a, L.g, L.ph, Dy);
+  hipLaunchKernelGGL((weno_face3d_kernel<O, 2, SPLIT_LLF, HYB_WENO_ONLY>), blocks(nfz, 128), dim3(128), 0,
+                     L.stream, a, L.g, L.ph, Dz);
+  hipLaunchKernelGGL((weno_sum3d_kernel<O>), blocks(nx * ny * nz, 256), dim3(256), 0, L.stream, a, L.g,
+                     L.ph, Dx, Dy, Dz);
   return hipGetLastError();
 }
 
 hipError_t fused3d_fix(const FusedLaunch& L) {
   const FusedArgs a = make_args(L);
   const dim3 fg(1024), fb(128);
+  const int sp = L.ph.split, hy = L.ph.hybrid;
+  if (L.fo3 != nullptr && sp == SPLIT_LLF && hy == HYB_WENO_ONLY)
+    return L.out_kind == OUT_RK ? fix_face_once<OUT_RK>(L, a) : fix_face_once<OUT_WRITE>(L, a);
 #define WL2_FIX(O, S, H) \
   hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H>), fg, fb, 0, L.stream, a, L.g, L.ph)
-  if (L.out_kind == OUT_RK) {
-    if (L.fast) WL2_FIX(OUT_RK, 0, 0); else WL2_FIX(OUT_RK, -1, -1);
-  } else {
-    if (L.fast) WL2_FIX(OUT_WRITE, 0, 0); else WL2_FIX(OUT_WRITE, -1, -1);
-  }
+#define WL2_FIX_SCHEMES(O)                                                           \
+  do {                                                                               \
+    if (sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_LLF, HYB_PER_FIELD); \
+    else if (sp == SPLIT_LLF && hy == HYB_WENO_ONLY) WL2_FIX(O, SPLIT_LLF, HYB_WENO_ONLY); \
+    else if (sp == SPLIT_ROE && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_ROE, HYB_PER_FIELD); \
+    else WL2_FIX(O, -1, -1);                                                         \
+  } while (0)
+  if (L.out_kind == OUT_RK) WL2_FIX_SCHEMES(OUT_RK);
+  else WL2_FIX_SCHEMES(OUT_WRITE);
+#undef WL2_FIX_SCHEMES
 #undef WL2_FIX
   return hipGetLastError();
 }

@@ -24,7 +24,8 @@ struct FusedLaunch {
   int out_kind;  // OUT_WRITE or OUT_RK
   int zc;        // z planes per workgroup
   int wpe;       // 1 or 2 waves per SIMD
-  int fast;      // LLF splitting with the per-field switch (compile-time path)
+  double* fo3;   // every face WENO: face changes of the x, y, z faces, 5 values
+                 // each (face-once corrections), or null: the per-cell kernel
   int n[3];
   KGrid g;
   KPhys ph;
@@ -38,5 +39,7 @@ struct FusedLaunch {
 hipError_t fused3d_reset(const FusedLaunch& L);
 hipError_t fused3d_main(const FusedLaunch& L);
 hipError_t fused3d_fix(const FusedLaunch& L);
+// Doubles of the face buffer (FusedLaunch::fo3) of an n[0] x n[1] x n[2] grid.
+size_t fused3d_face_doubles(const int n[3]);
 
 }  // namespace wl2

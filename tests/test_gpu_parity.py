@@ -181,13 +181,47 @@ def test_hundred_steps_parity(orc, capi, case):
 
 @pytest.mark.parametrize("case,variant", [("sod200", "weno_only"), ("quad67x45", "weno_only"),
                                           ("turb16x12x10_mixed", "lf"), ("shu1600", "roe"),
-                                          ("quad40x36_mixed", "per_face")])
+                                          ("quad40x36_mixed", "per_face"),
+                                          ("turb16x12x10_mixed", "weno_only"),
+                                          ("turb20x18x17", "roe"),
+                                          ("turb20x18x17", "linear_only")])
 def test_hundred_steps_variants(orc, capi, case, variant):
+    """The 100-step bar, 1e-10, or ten times the conditioning of the run if
+    that is larger: the largest distance the oracle's own 100 steps move when
+    its state is perturbed by one ulp (relative N(0, 2.2e-16) noise) after
+    every step, over three seeds.  With the hybrid switch that distance is
+    ~1e-14 and the bar stays 1e-10; with every face WENO on the 3D fields the
+    weights (eps = 1e-20) amplify round-off to 4e-10 .. 2e-9."""
     say(f"[step100] case={case} variant={variant}")
     got, ref = _run_steps(orc, capi, case, 100, variant)
     err = z20(got, ref)
     say(f"    z20 = {err:.3e}")
-    assert err <= 1e-10
+    if err > 1e-10:  # measured only where the plain bar does not hold
+        spread = _oracle_spread(orc, capi, case, variant, 100)
+        say(f"    oracle spread under 1-ulp noise = {spread:.3e}")
+        assert err <= 10.0 * spread
+
+
+def _oracle_spread(orc, capi, case, variant, nsteps, seeds=3):
+    """Largest z20 distance between the oracle's nsteps and the same steps
+    (same dt sequence) with the state perturbed by one ulp after each."""
+    U, dx, bc = make_case(case)
+    po, _ = params_pair(orc, capi, shape_of(U), dx, bc=bc, **VARIANTS[variant])
+    ref = U.copy()
+    dts = []
+    for _ in range(nsteps):
+        dt, st = orc.step(ref, dx, G, po)
+        assert st == 0
+        dts.append(dt)
+    worst = 0.0
+    for seed in range(seeds):
+        rng = np.random.default_rng(1000 + seed)
+        V = U.copy()
+        for dt in dts:
+            orc.step(V, dx, G, po, dt)
+            V *= 1.0 + 2.2e-16 * rng.standard_normal(V.shape)
+        worst = max(worst, z20(V, ref))
+    return worst
 
 
 @pytest.mark.parametrize("case", ["turb20x18x17", "turb16x12x10_mixed"])
@@ -208,7 +242,8 @@ def test_3d_sweeps_path_parity(orc, capi, case):
     ("shu1600", "default"), ("reflect101", "default"), ("quad67x45", "default"),
     ("quad40x36_mixed", "default"), ("quad67x45", "weno_only"), ("sod200", "linear_only"),
     ("sod200", "weno_only"), ("shu1600", "roe"), ("adv128", "default"), ("tiny5", "default"),
-    ("sod200", "lf")])
+    ("sod200", "lf"), ("turb20x18x17", "weno_only"), ("turb16x12x10_mixed", "weno_only"),
+    ("turb16x12x10_mixed", "linear_only"), ("turb20x18x17", "roe")])
 def test_advance_folded_cfl(orc, capi, case, variant):
     """weno_l2is_advance takes the CFL maximum of U^(n+1) from the last stage
     kernels (and from the nonlinear-correction kernel for the listed cells)
@@ -641,25 +676,36 @@ def test_gpu_design_order_smooth_advection(capi, axis, dim, hybrid, min_rate):
     assert rates[-1] > min_rate and rates[-2] > min_rate, (errs, rates)
 
 
-@pytest.mark.parametrize("shape", [(24, 24, 24), (40, 40, 36)])
-def test_3d_correction_modes_weno_only(orc, capi, shape):
-    """Every cell listed (WENO only): 13824 cells fit one lane per face in
-    the 3D correction kernel's launch, 57600 take a lane per cell; both one
-    SSP-RK3 step within 1e-12 of the oracle."""
+@pytest.mark.parametrize("shape,bc", [((24, 24, 24), [0] * 6), ((40, 40, 36), [0] * 6),
+                                      ((33, 29, 17), [1, 1, 2, 2, 0, 0]),
+                                      ((41, 37, 20), [2, 2, 1, 1, 1, 1])])
+def test_3d_correction_modes_weno_only(orc, capi, shape, bc):
+    """Every face WENO: the default corrections compute each face once (face
+    buffer, boundary faces included); the per-cell kernel (WL2_PATH_FUSED_CELLS)
+    takes one lane per face below 16384 cells and one lane per cell above.
+    Both give the same bits for an SSP-RK3 step and for dU/dt, within 1e-12
+    of the oracle."""
     import torch
     nx, ny, nz = shape
     U, dx = _turb_jump(nx, ny, nz, 9)
-    po, pg = params_pair(orc, capi, shape, dx, bc=[0] * 6, hybrid=2)
-    ctx = capi.Context(nx, ny, nz, dx, G, pg)
-    Ud = to_dev(U)
-    ctx.step(Ud)
-    torch.cuda.synchronize()
-    assert ctx.status() == 0
-    got = to_host(Ud)
-    ctx.close()
+    po, pg = params_pair(orc, capi, shape, dx, bc=bc, hybrid=2)
+    out = {}
+    for path in (capi.PATH_AUTO, capi.PATH_FUSED_CELLS):
+        ctx = capi.Context(nx, ny, nz, dx, G, pg)
+        ctx.tune(path)
+        Ud = to_dev(U)
+        d = torch.empty_like(Ud)
+        ctx.rhs(Ud, d)
+        ctx.step(Ud)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        out[path] = (to_host(Ud), to_host(d))
+        ctx.close()
+    a, b = out[capi.PATH_AUTO], out[capi.PATH_FUSED_CELLS]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     Uo = U.copy()
     _, st = orc.step(Uo, dx, G, po)
     assert st == 0
-    err = z20(got, Uo)
-    say(f"    {shape} WENO only: z20 = {err:.3e}")
+    err = z20(a[0], Uo)
+    say(f"    {shape} bc={bc} WENO only: z20 = {err:.3e}")
     assert err <= 1e-12
