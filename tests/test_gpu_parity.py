@@ -676,6 +676,28 @@ def test_gpu_design_order_smooth_advection(capi, axis, dim, hybrid, min_rate):
     assert rates[-1] > min_rate and rates[-2] > min_rate, (errs, rates)
 
 
+def test_3d_weno_only_register_budgets(capi):
+    """Every face WENO at one wave per SIMD: the stage kernel is then the
+    build that reads the scheme at run time and still fills the correction
+    list, which the face-once corrections ignore (every cell needs all six
+    faces either way): the same bits as the default budget."""
+    import torch
+    nx, ny, nz = 37, 29, 21
+    U, dx = _turb_jump(nx, ny, nz, 4)
+    pg = capi.params_default(nx, ny, nz, dx, bc=[0, 0, 2, 2, 1, 1], hybrid=2)
+    out = []
+    for wpe in (0, 1):
+        ctx = capi.Context(nx, ny, nz, dx, G, pg)
+        ctx.tune(capi.PATH_AUTO, 0, wpe)
+        Ud = to_dev(U)
+        ctx.advance(Ud, 3, 1e300)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        out.append(to_host(Ud))
+        ctx.close()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("shape,bc", [((24, 24, 24), [0] * 6), ((40, 40, 36), [0] * 6),
                                       ((33, 29, 17), [1, 1, 2, 2, 0, 0]),
                                       ((41, 37, 20), [2, 2, 1, 1, 1, 1])])
