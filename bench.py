@@ -107,8 +107,9 @@ def variants_3d(torch, capi, U0, dx, steps=10):
 def other_configs(torch, capi, workloads):
     """The 1D and 2D workloads run to their end: Sod 200 to t = 0.2,
     Shu-Osher 1600 to t = 1.8 (transmissive), the interacting blast waves on
-    400 cells to t = 0.038 (reflective walls, Roe splitting), 2D
-    four-quadrant 1024^2 for 200 steps.  Each through weno_l2is_advance on
+    400 cells to t = 0.038 (reflective walls, Roe splitting), the
+    broadband sound packet on 128 cells for one period (periodic, CFL 0.2),
+    2D four-quadrant 1024^2 for 200 steps.  Each through weno_l2is_advance on
     the fused 1D/2D kernel, timed with events on the library's stream after
     one untimed warm-up run."""
     out = {}
@@ -120,6 +121,9 @@ def other_configs(torch, capi, workloads):
     U, dx = workloads.blast_waves(400)
     cases.append(("blast_waves400_t0.038", U, dx, (400, 1, 1), 0.038, None,
                   {"split": 2, "bc": [2, 2, 1, 1, 1, 1]}))
+    U, dx = workloads.sound_packet(128)
+    cases.append(("sound_packet128_t1", U, dx, (128, 1, 1), 1.0, None,
+                  {"cfl": 0.2, "bc": [0, 0, 1, 1, 1, 1]}))
     U, dx, _ = workloads.four_quadrant_2d(1024, 1024, 2024)
     cases.append(("quad2d_1024x1024_200steps", U, dx, (1024, 1024, 1), 1e300, 200, {}))
     for name, U0, dx, shape, t_end, nsteps, kw in cases:

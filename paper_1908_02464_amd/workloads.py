@@ -54,6 +54,27 @@ def sod(n=200):
     return riemann_1d(n, *SOD)
 
 
+def sound_packet(n=128, seed=0, k0=12.0, eps=1e-3, gamma=GAMMA):
+    """Broadband acoustic packet on [0,1], periodic (Sec. 4.1, Eq.(36)-(37)):
+    p = p0 (1 + eps sum_{k=0}^{n/2} sqrt(E_p(k)) sin(2 pi k (x + phi_k))) with
+    E_p(k) = (k/k0)^4 exp(-2 (k/k0)^2) and phases phi_k uniform in [0,1),
+    isentropic rho = rho0 (p/p0)^(1/gamma), and the velocity of a
+    right-running simple wave u = u0 + 2 (c - c0)/(gamma - 1) (the printed
+    velocity is garbled; this is the reading).  rho0 = 1, p0 = 1/gamma
+    (c0 = 1), u0 = 0, so one period is t = 1."""
+    x, dx = centres(n, 0.0, 1.0)
+    rng = np.random.default_rng(seed)
+    k = np.arange(n // 2 + 1, dtype=np.float64)
+    phi = rng.random(k.size)
+    amp = np.sqrt((k / k0) ** 4 * np.exp(-2.0 * (k / k0) ** 2))
+    p0, rho0 = 1.0 / gamma, 1.0
+    p = p0 * (1.0 + eps * (amp[:, None] * np.sin(2.0 * np.pi * k[:, None] * (x[None, :] + phi[:, None]))).sum(0))
+    rho = rho0 * (p / p0) ** (1.0 / gamma)
+    c = np.sqrt(gamma * p / rho)
+    u = 2.0 * (c - 1.0) / (gamma - 1.0)
+    return conserved(rho, [u], p, gamma).reshape(3, 1, 1, n), dx
+
+
 def blast_waves(n=400, gamma=GAMMA):
     """Two interacting blast waves on [0,1] (Sec. 4.3): rho = 1, u = 0 and
     p = 1000 / 0.01 / 100 on [0, 0.1) / [0.1, 0.9) / [0.9, 1]; reflective

@@ -430,6 +430,38 @@ def test_blast_waves_full_run(orc, capi, split):
     assert abs(m1[2] - m0[2]) <= 1e-12 * m0[2]
 
 
+def test_sound_packet_full_run(orc, capi):
+    """Broadband acoustic packet (Sec. 4.1: 128 cells, k0 = 12, CFL 0.2,
+    periodic) advanced on the device clock for one period (641 steps): the
+    oracle's step count and state within the 100-step bar (the oracle
+    perturbed by one ulp after every step moves by 4e-12 on this run);
+    every face on the linear branch at the start, as in the oracle."""
+    import torch
+    say("[sound packet] 128 cells to t=1")
+    U, dx = w.sound_packet(128)
+    po, pg = params_pair(orc, capi, (128, 1, 1), dx, bc=[0, 0, 1, 1, 1, 1], cfl=0.2)
+    Uo = U.copy()
+    t, n, st = orc.run(Uo, dx, G, po, 1.0)
+    assert st == 0 and t == 1.0
+    ctx = capi.Context(128, 1, 1, dx, G, pg)
+    Ud = to_dev(U)
+    fl = torch.zeros(3 * 129, dtype=torch.uint8, device="cuda")
+    sg = torch.zeros(3 * 129, dtype=torch.float64, device="cuda")
+    ctx.face_debug(Ud, 0, fl, sg)
+    ctx.set_time(0.0)
+    ctx.advance(Ud, n + 10, 1.0)
+    tg, _, k = ctx.clock()
+    stg = ctx.status()
+    ctx.close()
+    torch.cuda.synchronize()
+    assert bool(fl.all())
+    got = to_host(Ud).reshape(U.shape)
+    err = z20(got, Uo)
+    say(f"    steps oracle={n} gpu={k} z20={err:.3e}")
+    assert stg == 0 and tg == 1.0 and k == n
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("n,bc", [(1, 1), (2, 0), (3, 1), (63, 1), (64, 2), (1008, 1), (1024, 0),
                                   (1025, 1)])
 def test_advance_1d_sizes(orc, capi, n, bc):

@@ -7,6 +7,8 @@
 * Conservation to round-off on periodic grids, free-stream preservation,
   mirror symmetry, reflective walls equal the mirror-extended periodic
   problem, and 1D data embedded in 2D/3D (any axis) gives the 1D answer.
+* The paper's interacting blast waves (Sec. 4.3) and broadband sound packet
+  (Sec. 4.1): physical, conservative, and convergent under refinement.
 """
 import json
 import os
@@ -221,6 +223,47 @@ def test_blast_waves_refinement(orc):
     fine = run(1600)
     errs = [np.abs(run(n) - fine.reshape(n, -1).mean(axis=1)).mean() for n in (100, 200, 400)]
     assert errs[0] > 1.5 * errs[1] > 2.25 * errs[2], errs
+
+
+def _fourier_at(field, n):
+    """The periodic cell-centred field on [0,1), interpolated to the n
+    centres of a coarser grid through its Fourier series (exact for a
+    band-limited field)."""
+    m = field.size
+    c = np.fft.rfft(field) / m
+    k = np.arange(c.size)
+    wgt = np.where((k == 0) | ((m % 2 == 0) & (k == m // 2)), 1.0, 2.0)
+    x = (np.arange(n) + 0.5) / n
+    return np.real((wgt * c)[None, :] * np.exp(2j * np.pi * k[None, :] * (x[:, None] - 0.5 / m))).sum(1)
+
+
+def test_sound_packet_refinement(orc):
+    """Broadband acoustic packet (Sec. 4.1: k0 = 12, eps = 1e-3, CFL 0.2,
+    periodic, one period): the small smooth waves keep every face on the
+    linear branch (detector far below its threshold), mass, momentum and
+    energy are conserved to round-off, and the pressure converges: against
+    a 1024-cell run, interpolated to the coarse centres through its Fourier
+    series, the error falls by more than 8x from 128 to 256 cells (9.3x
+    measured; the peak wavenumber has 10.7 points per wavelength at 128
+    cells, short of the fifth-order regime)."""
+    def run(n):
+        U, dx = w.sound_packet(n)
+        p = orc.params(n, 1, 1, dx, bc=[0, 0, 1, 1, 1, 1], cfl=0.2)
+        fl, _ = orc.face_debug(U, dx, G, p, 0)
+        assert fl.all()
+        m0 = U.sum(axis=(1, 2, 3))
+        t, _, st = orc.run(U, dx, G, p, 1.0)
+        assert st == 0 and t == 1.0
+        m1 = U.sum(axis=(1, 2, 3))
+        assert np.all(np.abs(m1 - m0) <= 1e-12 * np.abs(m0).max())
+        return (G - 1.0) * (U[2, 0, 0] - 0.5 * U[1, 0, 0] ** 2 / U[0, 0, 0])
+    fine = run(1024)
+    errs = []
+    for n in (128, 256):
+        ref = _fourier_at(fine, n)
+        errs.append(np.sqrt(((run(n) - ref) ** 2).mean()) / np.sqrt(((ref - ref.mean()) ** 2).mean()))
+    assert errs[0] > 8.0 * errs[1], errs
+    assert errs[0] < 0.5, errs  # the packet survives one period at 128 cells
 
 
 def test_reflective_wall_equals_mirror_extended_periodic(orc):
