@@ -657,6 +657,84 @@ def test_full_size_sampled(orc, capi, which):
     ctx.close()
 
 
+def test_large_grid_64bit_indexing(orc, capi):
+    """A grid of 1024 x 1000 x 424 cells (434M cells: 2.17G values per state
+    array, past 2^31; edge tiles of 10 rows, a partial z chunk) built on the
+    device from smooth periodic index-space functions with a density contact
+    (so nonlinear faces occur at large offsets); one host copy feeds the
+    oracle.  Device CFL dt equal to the oracle's; dU/dt at sampled cells and
+    one SSP-RK3 step at sampled cells (oracle steps on periodic 21^3 sub-boxes)
+    within 1e-12.  About 94 GB of device memory."""
+    import torch
+    nx, ny, nz = 1024, 1000, 424
+    free, _ = torch.cuda.mem_get_info()
+    if free < 120e9:
+        pytest.skip(f"needs ~94 GB of free device memory, {free / 1e9:.0f} GB free")
+    say(f"[large] {nx}x{ny}x{nz}")
+    dx = 1.0 / nx
+    two_pi = 2.0 * np.pi
+    dev = "cuda"
+    ax = lambda n: (torch.arange(n, dtype=torch.float64, device=dev) + 0.5) / n
+    sx, sy, sz = ax(nx)[None, None, :], ax(ny)[None, :, None], ax(nz)[:, None, None]
+    Ud = torch.empty((5, nz, ny, nx), dtype=torch.float64, device=dev)
+    rho = 1.0 + 0.2 * torch.sin(two_pi * sx) * torch.cos(two_pi * sy) + 0.1 * torch.sin(two_pi * sz)
+    rho = rho + 0.5 * (sx < 0.25).to(torch.float64)  # a contact
+    u = 0.3 * torch.sin(two_pi * (sy + sz))
+    v = 0.3 * torch.sin(two_pi * (sz + sx))
+    wv = 0.3 * torch.sin(two_pi * (sx + sy))
+    p = 1.0 + 0.1 * torch.cos(two_pi * (sx + sy + sz))
+    Ud[0] = rho
+    Ud[1] = rho * u
+    Ud[2] = rho * v
+    Ud[3] = rho * wv
+    Ud[4] = p / (G - 1.0) + 0.5 * rho * (u * u + v * v + wv * wv)
+    del rho, u, v, wv, p
+    torch.cuda.synchronize()
+    U = Ud.cpu().numpy()
+    shape = (nx, ny, nz)
+    bc = [0] * 6
+    po, pg = params_pair(orc, capi, shape, dx, bc=bc)
+    ctx = capi.Context(*shape, dx, G, pg)
+    dt_g, st = ctx.cfl_dt(Ud)
+    dt_o, st_o = orc.cfl_dt(U, dx, G)
+    say(f"    dt gpu={dt_g!r} oracle={dt_o!r}")
+    assert st == 0 and st_o == 0 and dt_g == dt_o
+    rng = np.random.default_rng(7)
+    cells = _sample_cells(shape, 200, rng)
+    cells = np.concatenate([cells, [nx * ny * nz - 1, (nx * ny * nz) // 2 + 12345]])
+    cells_d = torch.from_numpy(cells).to(dev)
+    out = torch.empty_like(Ud)
+    ctx.rhs(Ud, out)
+    got = out.reshape(5, -1)[:, cells_d].cpu().numpy()
+    del out
+    ref = orc.rhs_at(U, dx, G, po, cells)
+    Uflat = U.reshape(5, -1)
+    err = rhs_err(got, ref, Uflat, dt_o)
+    say(f"    rhs sampled cells={cells.size} err(state units)={err:.3e}")
+    assert err <= 1e-12
+    ctx.step(Ud)
+    _, dt_used = ctx.time()
+    assert dt_used == dt_o and ctx.status() == 0
+    R = 10
+    picks = rng.choice(cells, 10, replace=False)
+    U1c = Ud.reshape(5, -1)[:, torch.from_numpy(picks).to(dev)].cpu().numpy()
+    ctx.close()
+    del Ud
+    torch.cuda.empty_cache()
+    scale = np.abs(Uflat).max(axis=1)
+    worst = 0.0
+    for j, c in enumerate(picks):
+        x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+        sub = [np.arange(q - R, q + R + 1) % n for q, n in zip((x, y, z), shape)]
+        box = np.ascontiguousarray(U[:, sub[2][:, None, None], sub[1][None, :, None], sub[0][None, None, :]])
+        pb = orc.params(2 * R + 1, 2 * R + 1, 2 * R + 1, dx, bc=[1] * 6, thr_L=list(po.thr_L))
+        orc.step(box, dx, G, pb, dt_o)
+        ref_c = box[:, R, R, R]
+        worst = max(worst, float(np.max(np.abs(U1c[:, j] - ref_c) / np.maximum(np.abs(ref_c), scale))))
+    say(f"    one-step sampled z20={worst:.3e}")
+    assert worst <= 1e-12
+
+
 def _advection_state(n, axis, dim, t=0.0):
     """rho = 1 + 0.2 sin(pi (s - t)), velocity 1 along `axis` (0 x, 1 y, 2 z),
     p = 1 on [-1, 1] along the axis; the other extents are 4 cells of the
