@@ -42,7 +42,7 @@ extern "C" {
 enum {
   WL2_OK = 0,
   WL2_E_NULL = -1,        /* a required pointer is NULL                     */
-  WL2_E_SHAPE = -2,       /* n < 1, nz > 1 with ny == 1, or too large       */
+  WL2_E_SHAPE = -2,       /* n < 1, nz > 1 with ny == 1, or 2^32 cells+     */
   WL2_E_PARAM = -3,       /* dx, gamma, cfl, thresholds or enums invalid    */
   WL2_E_BC = -4,          /* unpaired periodic side, reflective with n < 3  */
   WL2_E_HIP = -5,         /* a HIP runtime call failed                       */

@@ -42,7 +42,8 @@ inline int validate_grid(int nx, int ny, int nz, double dx, double gamma,
   if (!p) return WL2_E_NULL;
   if (nx < 1 || ny < 1 || nz < 1) return WL2_E_SHAPE;
   if (nz > 1 && ny < 2) return WL2_E_SHAPE;
-  if ((long long)nx * ny * nz > (1LL << 40)) return WL2_E_SHAPE;
+  // correction lists count and address cells with 32 bits
+  if ((long long)nx * ny * nz > 0xffffffffLL) return WL2_E_SHAPE;
   if (!(dx > 0.0) || !(dx < 1e300) || !(gamma > 1.0) || !(gamma < 1e300)) return WL2_E_PARAM;
   if (!(p->cfl > 0.0) || !(p->c_reg >= 0.0) || !(p->eps_weno >= 0.0) || !(p->thr_C >= 0.0) ||
       p->thr_alpha < 0 || p->thr_alpha > 64)

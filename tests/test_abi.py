@@ -79,6 +79,8 @@ def test_arguments_refused_before_any_device_call():
     assert create(0, 1, 1) == capi.E_SHAPE            # empty grid
     assert create(8, 0, 1) == capi.E_SHAPE
     assert create(8, 1, 4) == capi.E_SHAPE            # nz > 1 with ny == 1
+    assert create(65536, 65536, 1) == capi.E_SHAPE     # 2^32 cells: lists address 32 bits
+    assert create(4096, 1024, 1024) == capi.E_SHAPE
     assert create(8, 1, 1, dx=-0.1) == capi.E_PARAM
     assert create(8, 1, 1, dx=float("inf")) == capi.E_PARAM
     assert create(8, 1, 1, gamma=1.0) == capi.E_PARAM
