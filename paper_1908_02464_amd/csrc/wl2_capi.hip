@@ -213,10 +213,16 @@ int row_ych(const weno_l2is_ctx* c) {
   if (c->dim == 1) return 1;
   const int cap = ROW_MAX_YCH < c->n[1] ? ROW_MAX_YCH : c->n[1];
   if (c->zchunk > 0) return c->zchunk < cap ? c->zchunk : cap;
+  // One wavefront per item and two per SIMD: 2048 items run at once.  If
+  // the grid fits one such round with at most 12 rows per item, the fewest
+  // rows that do (the most parallel single round); otherwise 11 rows (fewer
+  // warm-up rows per row computed; items then run in several rounds).
+  constexpr long long ROUND = 2048;
   const long long tiles = (c->n[0] + ROW_TILE - 1) / ROW_TILE;
-  int y = 6 < cap ? 6 : cap;
-  while (y > 2 && tiles * ((c->n[1] + y - 1) / y) < 1536) --y;
-  return y;
+  const int ymax = 12 < cap ? 12 : cap;
+  for (int y = 2; y <= ymax; ++y)
+    if (tiles * ((c->n[1] + y - 1) / y) <= ROUND) return y;
+  return 11 < cap ? 11 : cap;
 }
 
 // The counters of the next stage launch, clearing both if needed.
