@@ -36,6 +36,7 @@ struct weno_l2is_ctx {
   double* fo_D = nullptr;          // 2D face-once corrections: face changes per list entry
   unsigned int* fo_map = nullptr;  // and the cell -> list entry map (null: per-cell kernel)
   double* fo3 = nullptr;           // 3D, every face WENO: each face's change (face-once)
+  unsigned int* counts = nullptr;  // 3D: entries each stage-kernel workgroup listed
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
@@ -309,6 +310,8 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
   L.zc = fused_zchunk(c);
   L.wpe = c->wpe;  // the scheme's build is chosen from L.ph
   L.fo3 = c->path == WL2_PATH_FUSED_CELLS ? nullptr : c->fo3;
+  L.counts = c->counts;
+  L.offs = c->counts ? c->counts + fused3d_count_entries(c->n) : nullptr;
   for (int d = 0; d < 3; ++d) L.n[d] = c->n[d];
   L.g = c->g;
   L.ph = c->ph;
@@ -425,6 +428,10 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   // face once into a face buffer (15 doubles per cell)
   if (ok && c->dim == 3 && p->hybrid == WL2_HYB_WENO_ONLY && p->split == WL2_SPLIT_LLF)
     ok = hipMalloc(&c->fo3, sizeof(double) * fused3d_face_doubles(c->n)) == hipSuccess;
+  // 3D: per-workgroup counts of the correction list and their prefix sums
+  if (ok && c->dim == 3)
+    ok = hipMalloc(&c->counts, sizeof(unsigned int) * (2 * fused3d_count_entries(c->n) + 1)) ==
+         hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
     (void)hipFree(c->U1);
@@ -434,6 +441,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
     (void)hipFree(c->fo_D);
     (void)hipFree(c->fo_map);
     (void)hipFree(c->fo3);
+    (void)hipFree(c->counts);
     (void)hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
@@ -454,6 +462,7 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   (void)hipFree(c->fo_D);
   (void)hipFree(c->fo_map);
   (void)hipFree(c->fo3);
+  (void)hipFree(c->counts);
   (void)hipFree(c->ctl);
   delete c;
 }

@@ -56,9 +56,27 @@ struct FusedArgs {
   unsigned long long* list;  // cells next to a face that needs the WENO flux
   unsigned int* list_n;      // number of entries in list
   unsigned int* list_clear;  // the next stage's counter, zeroed by the correction kernel
+  unsigned int* counts;      // entries each workgroup listed in its list region
+  unsigned int* offs;        // exclusive prefix sums of counts (nreg + 1 values)
   StepCtl* cfl;              // RK: if set, fold the CFL speed of the new state
                              // into cfl->smax / status (next step's dt)
 };
+
+// The correction list is cut into one region per workgroup of the stage
+// kernel, so that no global counter is shared: the regions of all
+// workgroups tile [0, ncell) in logical tile order, each as large as the
+// workgroup's in-grid cells (only the last tile along x, the last tile row
+// and the last z chunk are partial, so every region before a given one is
+// full-sized).  First list index of the region of logical tile r.
+__device__ __forceinline__ long long list_region_start(const FusedArgs& a, const KGrid& g, int r) {
+  const int ttx = r % a.tiles_x, rest = r / a.tiles_x;
+  const int tty = rest % a.tiles_y, tzc = rest / a.tiles_y;
+  const long long z0 = (long long)tzc * a.zc;
+  const long long planes = min((long long)a.zc, (long long)g.n[2] - z0);
+  const long long vr = min(FT_Y, g.n[1] - tty * FT_Y);
+  return (long long)g.n[0] * g.n[1] * z0 +
+         ((long long)tty * FT_Y * g.n[0] + (long long)ttx * FT_X * vr) * planes;
+}
 
 typedef __attribute__((address_space(3))) double lds_wdouble;
 typedef const __attribute__((address_space(3))) double lds_double;
@@ -204,6 +222,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   __shared__ double sfy[NV][NYF];            // y-face fluxes of plane z
   __shared__ double2 swin[2 * RING_SLOT];    // two oldest cells of each z window
   __shared__ unsigned char sgx[NXF], sgy[NYF];  // face needs the nonlinear flux
+  __shared__ unsigned int s_cnt;                 // entries listed by this workgroup
 
   double dt = 0.0;
   if (OUT == OUT_RK) {
@@ -238,6 +257,11 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   const int lds_own = (oy + 3) * FP_ROW + (ox + 3);
   const Col ocol = make_col(g, gx, gy);
   const long long oout = (long long)gx + (long long)gy * g.stride[1];
+  // this workgroup's region of the correction list (its count is kept in
+  // LDS and stored at the end; made visible by the barriers of the first
+  // plane before any append)
+  const long long reg0 = list_region_start(a, g, logical);
+  if (t == 0) s_cnt = 0u;
 
   // halo cell of this thread (t < NHALO): tile-relative (hc, hr)
   int hc = 0, hr = 0;
@@ -379,11 +403,11 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
           const int lane = threadIdx.x & 63;
           const int leader = __ffsll((long long)ball) - 1;
           unsigned int basei = 0;
-          if (lane == leader) basei = atomicAdd(a.list_n, (unsigned int)__popcll(ball));
+          if (lane == leader) basei = atomicAdd(&s_cnt, (unsigned int)__popcll(ball));
           basei = __shfl(basei, leader, 64);
           if (cm) {
             const unsigned int rank = __popcll(ball & ((1ull << lane) - 1ull));
-            a.list[basei + rank] = ((unsigned long long)off << 8) | cm;
+            a.list[reg0 + basei + rank] = ((unsigned long long)off << 8) | cm;
           }
         }
       }
@@ -413,6 +437,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       for (int v = 0; v < NV; ++v) Fzp[v] = Fz[v];
     }
   }
+  if (HYB != HYB_WENO_ONLY) {
+    __syncthreads();  // every append of the workgroup is counted
+    if (t == 0) a.counts[logical] = s_cnt;
+  }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }
 
@@ -434,23 +462,10 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
     if (!(dt > 0.0)) return;
     scale = a.rk_b * dt;
   }
-  // every face WENO (compile-time): every in-grid cell has all six faces
-  // flagged, so the cells are walked in index order instead of a list (the
-  // same cells and masks a list would hold; each cell's result does not
-  // depend on the order)
-  constexpr bool dense = HYB == HYB_WENO_ONLY;
-  const unsigned int n = dense ? (unsigned int)g.ncell : *a.list_n;
   double cfl_max = 0.0;
   bool cfl_bad = false;
-  const unsigned int threads = gridDim.x * blockDim.x;
-  const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  // one lane per face whenever the launch has a group for every cell (for
-  // 3D lists measured faster than a lane per cell up to that size: 12 % on
-  // the 256^3 turbulence, where 1D/2D lists keep the FIX_GROUPED_LANES rule)
-  const bool grouped = n <= threads / GRP;
-  const unsigned int step = grouped ? threads / GRP : threads;
-  for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step) {
-    const unsigned long long e = dense ? (((unsigned long long)i << 8) | 0x3full) : a.list[i];
+  // one listed cell (entry e): eight lanes of a group when grouped, else one lane
+  auto fix_one = [&](unsigned long long e, bool grouped) {
     const long long off = (long long)(e >> 8);
     const unsigned cm = (unsigned)(e & 0xffu);
     const int x = (int)(off % g.n[0]);
@@ -470,6 +485,38 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
         const double m[3] = {un[1], un[2], un[3]};
         cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
       }
+    }
+  };
+  if (HYB == HYB_WENO_ONLY) {
+    // every face WENO (compile-time): every in-grid cell has all six faces
+    // flagged, so the cells are walked in index order instead of a list (the
+    // same cells and masks a list would hold; each cell's result does not
+    // depend on the order)
+    const unsigned int n = (unsigned int)g.ncell;
+    const unsigned int threads = gridDim.x * blockDim.x;
+    const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool grouped = n <= threads / GRP;
+    const unsigned int step = grouped ? threads / GRP : threads;
+    for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step)
+      fix_one(((unsigned long long)i << 8) | 0x3full, grouped);
+  } else {
+    // the entries of all list regions as one index space (offsets from
+    // list_scan_kernel); entry i lies in the region r with
+    // offs[r] <= i < offs[r + 1], found by bisection
+    const int nreg = a.tiles_x * a.tiles_y * ((g.n[2] + a.zc - 1) / a.zc);
+    const unsigned int n = a.offs[nreg];
+    const unsigned int threads = gridDim.x * blockDim.x;
+    const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool grouped = n <= threads / GRP;
+    const unsigned int step = grouped ? threads / GRP : threads;
+    for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step) {
+      int lo = 0, hi = nreg;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.offs[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      fix_one(a.list[list_region_start(a, g, lo) + (i - a.offs[lo])], grouped);
     }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
@@ -552,6 +599,34 @@ __global__ __launch_bounds__(256) void weno_sum3d_kernel(FusedArgs a, KGrid g, K
     }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
+}
+
+// Exclusive prefix sums of the per-workgroup list counts: offs[r] = entries
+// of the regions before r, offs[nreg] = all entries.  One workgroup of 1024
+// threads, each summing a contiguous run of counts.
+static __global__ __launch_bounds__(1024) void list_scan_kernel(const unsigned int* counts, int nreg,
+                                                                unsigned int* offs) {
+  __shared__ unsigned int part[1024];
+  const int t = threadIdx.x;
+  const int per = (nreg + 1023) / 1024;
+  const int b = t * per, e = min(b + per, nreg);
+  unsigned int sum = 0u;
+  for (int r = b; r < e; ++r) sum += counts[r];
+  part[t] = sum;
+  __syncthreads();
+  // inclusive scan of the 1024 partial sums (Hillis-Steele)
+  for (int d = 1; d < 1024; d <<= 1) {
+    const unsigned int v = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned int run = t > 0 ? part[t - 1] : 0u;
+  for (int r = b; r < e; ++r) {
+    offs[r] = run;
+    run += counts[r];
+  }
+  if (t == 1023) offs[nreg] = part[1023];
 }
 
 [[maybe_unused]] static __global__ void reset_list_kernel(unsigned int* list_n) {

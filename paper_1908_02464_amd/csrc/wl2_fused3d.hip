@@ -20,6 +20,8 @@ FusedArgs make_args(const FusedLaunch& L) {
   a.list = L.list;
   a.list_n = L.list_n;
   a.list_clear = L.list_clear;
+  a.counts = L.counts;
+  a.offs = L.offs;
   a.cfl = L.out_kind == OUT_RK ? L.cfl : nullptr;
   a.tiles_x = (L.n[0] + FT_X - 1) / FT_X;
   a.tiles_y = (L.n[1] + FT_Y - 1) / FT_Y;
@@ -109,6 +111,11 @@ hipError_t fused3d_fix(const FusedLaunch& L) {
   const int sp = L.ph.split, hy = L.ph.hybrid;
   if (L.fo3 != nullptr && sp == SPLIT_LLF && hy == HYB_WENO_ONLY)
     return L.out_kind == OUT_RK ? fix_face_once<OUT_RK>(L, a) : fix_face_once<OUT_WRITE>(L, a);
+  if (!(sp == SPLIT_LLF && hy == HYB_WENO_ONLY)) {
+    // offsets of the per-workgroup list regions (the dense form needs none)
+    const int nreg = a.tiles_x * a.tiles_y * ((L.n[2] + a.zc - 1) / a.zc);
+    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts, nreg, a.offs);
+  }
 #define WL2_FIX(O, S, H) \
   hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H>), fg, fb, 0, L.stream, a, L.g, L.ph)
 #define WL2_FIX_SCHEMES(O)                                                           \

@@ -20,6 +20,9 @@ struct FusedLaunch {
   unsigned long long* list;
   unsigned int* list_n;      // this stage's list counter
   unsigned int* list_clear;  // the next stage's, zeroed by the correction kernel
+  unsigned int* counts;      // entries each stage-kernel workgroup listed in its
+                             // region of `list` (fused3d_count_entries of them)
+  unsigned int* offs;        // their exclusive prefix sums (one more entry)
   double rk_a, rk_b;
   int out_kind;  // OUT_WRITE or OUT_RK
   int zc;        // z planes per workgroup
@@ -41,5 +44,10 @@ hipError_t fused3d_main(const FusedLaunch& L);
 hipError_t fused3d_fix(const FusedLaunch& L);
 // Doubles of the face buffer (FusedLaunch::fo3) of an n[0] x n[1] x n[2] grid.
 size_t fused3d_face_doubles(const int n[3]);
+// Entries of the per-workgroup count array (FusedLaunch::counts): enough for
+// any z chunk (one workgroup per column tile and plane at most).
+inline size_t fused3d_count_entries(const int n[3]) {
+  return (size_t)((n[0] + FT_X - 1) / FT_X) * ((n[1] + FT_Y - 1) / FT_Y) * n[2];
+}
 
 }  // namespace wl2
