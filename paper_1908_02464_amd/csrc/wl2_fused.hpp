@@ -68,6 +68,10 @@ struct FusedArgs {
 // workgroup's in-grid cells (only the last tile along x, the last tile row
 // and the last z chunk are partial, so every region before a given one is
 // full-sized).  First list index of the region of logical tile r.
+// Regions up to which the correction kernel forms the list offsets itself
+// (in LDS); beyond, a one-workgroup scan kernel writes them.
+constexpr int SCAN_LDS = 8192;
+
 __device__ __forceinline__ long long list_region_start(const FusedArgs& a, const KGrid& g, int r) {
   const int ttx = r % a.tiles_x, rest = r / a.tiles_x;
   const int tty = rest % a.tiles_y, tzc = rest / a.tiles_y;
@@ -500,11 +504,38 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
     for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step)
       fix_one(((unsigned long long)i << 8) | 0x3full, grouped);
   } else {
-    // the entries of all list regions as one index space (offsets from
-    // list_scan_kernel); entry i lies in the region r with
-    // offs[r] <= i < offs[r + 1], found by bisection
+    // the entries of all list regions as one index space: entry i lies in
+    // the region r with offs[r] <= i < offs[r + 1], found by bisection.  Up
+    // to SCAN_LDS regions every block forms the offsets in LDS from the
+    // counts; beyond, list_scan_kernel has written them to a.offs.
     const int nreg = a.tiles_x * a.tiles_y * ((g.n[2] + a.zc - 1) / a.zc);
-    const unsigned int n = a.offs[nreg];
+    __shared__ unsigned int soffs[SCAN_LDS + 1];
+    __shared__ unsigned int spart[128];
+    const unsigned int* offs = a.offs;
+    if (nreg <= SCAN_LDS) {
+      const int t = threadIdx.x, nt = blockDim.x;  // 128
+      const int per = (nreg + nt - 1) / nt;
+      const int b = t * per, e = min(b + per, nreg);
+      unsigned int sum = 0u;
+      for (int r = b; r < e; ++r) sum += a.counts[r];
+      spart[t] = sum;
+      __syncthreads();
+      for (int d = 1; d < nt; d <<= 1) {
+        const unsigned int v = t >= d ? spart[t - d] : 0u;
+        __syncthreads();
+        spart[t] += v;
+        __syncthreads();
+      }
+      unsigned int run = t > 0 ? spart[t - 1] : 0u;
+      for (int r = b; r < e; ++r) {
+        soffs[r] = run;
+        run += a.counts[r];
+      }
+      if (t == nt - 1) soffs[nreg] = spart[nt - 1];
+      __syncthreads();
+      offs = soffs;
+    }
+    const unsigned int n = offs[nreg];
     const unsigned int threads = gridDim.x * blockDim.x;
     const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool grouped = n <= threads / GRP;
@@ -513,10 +544,10 @@ __global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, K
       int lo = 0, hi = nreg;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (a.offs[mid] <= i) lo = mid;
+        if (offs[mid] <= i) lo = mid;
         else hi = mid;
       }
-      fix_one(a.list[list_region_start(a, g, lo) + (i - a.offs[lo])], grouped);
+      fix_one(a.list[list_region_start(a, g, lo) + (i - offs[lo])], grouped);
     }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);

@@ -112,9 +112,11 @@ hipError_t fused3d_fix(const FusedLaunch& L) {
   if (L.fo3 != nullptr && sp == SPLIT_LLF && hy == HYB_WENO_ONLY)
     return L.out_kind == OUT_RK ? fix_face_once<OUT_RK>(L, a) : fix_face_once<OUT_WRITE>(L, a);
   if (!(sp == SPLIT_LLF && hy == HYB_WENO_ONLY)) {
-    // offsets of the per-workgroup list regions (the dense form needs none)
+    // offsets of the per-workgroup list regions (the dense form needs none;
+    // up to SCAN_LDS regions the correction kernel forms them itself)
     const int nreg = a.tiles_x * a.tiles_y * ((L.n[2] + a.zc - 1) / a.zc);
-    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts, nreg, a.offs);
+    if (nreg > SCAN_LDS)
+      hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts, nreg, a.offs);
   }
 #define WL2_FIX(O, S, H) \
   hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H>), fg, fb, 0, L.stream, a, L.g, L.ph)
