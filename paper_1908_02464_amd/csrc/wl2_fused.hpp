@@ -454,8 +454,12 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
 // a short list, one lane per cell for a long one, with the same bits.  Each
 // cell is owned by one lane (group), so the result does not depend on
 // scheduling.  With a.cfl set, the CFL speed of the corrected cell is folded.
+// Two waves per SIMD (at most 256 registers; the default scheme's build
+// spills 104 bytes): the stencil loads of a face are latency-bound, and at
+// 256^3 two waves beat one by 16 % once shocklets form (3.18 against 3.78
+// ms per step at 2.9 % WENO face-fields) and by 4 % in the smooth regime.
 template <int OUT, int SPLIT, int HYB>
-__global__ __launch_bounds__(128) void weno_fix3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
+__global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
   constexpr int GRP = 8;
   // the next stage's list starts empty (no kernel of this stage uses it)
