@@ -361,6 +361,7 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       load_col_raw<NV>(a.Uk, g, hcol, z + 1, hpre);
     }
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);  // face rounds at normal priority
     __builtin_amdgcn_sched_barrier(0);
     // x faces: thread t < 255 -> row t/17, face fx = t%17 at x0 + fx - 1/2
     if (t < NXF && t / (FT_X + 1) < rows_v && t % (FT_X + 1) <= cols_v) {
@@ -382,6 +383,11 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       for (int v = 0; v < NV; ++v) sfy[v][t] = F[v];
     }
     __syncthreads();
+    // raised wave priority from here (z face, stores, the next plane's loads
+    // and records) to the next plane's first barrier: the waves that issue
+    // memory requests go before the other workgroup's face rounds (measured
+    // 1.2-1.7 % faster at 256^3; a wave's priority is local to this kernel)
+    __builtin_amdgcn_s_setprio(2);
     __builtin_amdgcn_sched_barrier(0);
     if (valid) {
       // z face z + 1/2: cells z-2, z-1 (ring), z .. z+3 (registers)
