@@ -265,6 +265,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
         row_load_raw<NV>(a.Uk, g, hxy, y + 1, hpre);
       }
       __syncthreads();
+      __builtin_amdgcn_s_setprio(0);
       // x face on the left of column x0+lane (cells x-3 .. x+2 = slots lane .. lane+5)
       double Fx[NV];
       const unsigned mx =
@@ -288,6 +289,10 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
           own ? ((mx ? 1u : 0u) | (mxr ? 2u : 0u) | (yprev ? 4u : 0u) | (ycur ? 8u : 0u)) : 0u;
       list_append(a, off, cm);
       yprev = ycur;
+      // raised wave priority from the stores through the next row's loads and
+      // records to its barrier, normal for the faces (measured 1.6 % faster
+      // on 2D 1024^2; local to this kernel)
+      __builtin_amdgcn_s_setprio(2);
       if (own) {
         double un[NV];
 #pragma unroll
