@@ -44,7 +44,8 @@ enum {
   WL2_E_NULL = -1,        /* a required pointer is NULL                     */
   WL2_E_SHAPE = -2,       /* n < 1, nz > 1 with ny == 1, or 2^32 cells+     */
   WL2_E_PARAM = -3,       /* dx, gamma, cfl, thresholds or enums invalid    */
-  WL2_E_BC = -4,          /* unpaired periodic side, reflective with n < 3  */
+  WL2_E_BC = -4,          /* unpaired periodic side, reflective with n < 3,
+                             inflow misplaced or its state not set          */
   WL2_E_HIP = -5,         /* a HIP runtime call failed                       */
   WL2_E_NOMEM = -6,       /* device allocation failed                        */
   WL2_E_BUDGET = -7,      /* batch: HBM budget or slot table exhausted      */
@@ -52,7 +53,15 @@ enum {
   WL2_S_NONPHYSICAL = 1   /* rho <= 0, p <= 0 or non-finite state detected   */
 };
 
-enum { WL2_BC_PERIODIC = 0, WL2_BC_TRANSMISSIVE = 1, WL2_BC_REFLECTIVE = 2 };
+/* Boundary rule of a side, applied through three ghost cells (the paper
+ * names the conditions of its tests only): PERIODIC wraps (both sides of a
+ * direction); TRANSMISSIVE copies the boundary cell (outflow); REFLECTIVE
+ * mirrors the interior with the normal momentum negated (Sec. 4.3, 4.7);
+ * INFLOW gives the ghosts a prescribed state per x line, set with
+ * weno_l2is_set_inflow (the left side of the jet of Sec. 4.7; allowed on the
+ * x- side of a 1D or 2D grid held by a context only). */
+enum { WL2_BC_PERIODIC = 0, WL2_BC_TRANSMISSIVE = 1, WL2_BC_REFLECTIVE = 2,
+       WL2_BC_INFLOW = 3 };
 
 /* Flux-splitting speed alpha^s of Eq.(21): LLF = max over the six stencil
  * cells of |lambda^s(U_m)| (the hot path); LF = max over the whole grid per
@@ -127,10 +136,23 @@ int weno_l2is_step(weno_l2is_ctx *ctx, double *U, double dt);
 int weno_l2is_advance(weno_l2is_ctx *ctx, double *U, int n_steps,
                       double t_end);
 
+/* Ghost state of the inflow side (Sec. 4.7: the left boundary of the jet
+ * prescribes the state (rho, u, v, p) of its ghosts, one state inside the
+ * jet and another outside).  state: DEVICE pointer to the conserved state
+ * [nvar][ny] (x fastest layout of one column: element v*ny + y is variable
+ * v of the three ghost cells left of row y).  Copied into the context
+ * before the call returns; the caller keeps ownership.  The context must
+ * have been created with bc[0] == WL2_BC_INFLOW (else WL2_E_BC); until this
+ * call has been made, every call that evaluates the right-hand side
+ * (rhs_ctx, step, advance, face_debug) returns WL2_E_BC.  The stateless
+ * weno_l2is_rhs and the batch engine refuse WL2_BC_INFLOW (WL2_E_BC). */
+int weno_l2is_set_inflow(weno_l2is_ctx *ctx, const double *state);
+
 /* Reset the device clock of the context to t (for weno_l2is_advance). */
 int weno_l2is_set_time(weno_l2is_ctx *ctx, double t);
 
-/* CFL time step of U (device reduction).  If dt_host is not NULL the call
+/* CFL time step of U (device reduction; with an inflow side the speed of
+ * its ghost states bounds it too).  If dt_host is not NULL the call
  * synchronizes the stream and stores it.  Returns WL2_S_NONPHYSICAL if a
  * non-physical cell was found (only known when dt_host != NULL). */
 int weno_l2is_cfl_dt(weno_l2is_ctx *ctx, const double *U, double *dt_host);

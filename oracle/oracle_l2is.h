@@ -23,7 +23,8 @@
 extern "C" {
 #endif
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_REFLECTIVE = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_REFLECTIVE = 2,
+       ORC_BC_INFLOW = 3 /* x- side of a 1D/2D grid: ghosts = inflow[] */ };
 enum { ORC_SPLIT_LLF = 0, ORC_SPLIT_LF = 1, ORC_SPLIT_ROE = 2 };
 enum {
   ORC_HYB_PER_FIELD = 0,  /* linear flux for field s iff sigma^s < eps      */
@@ -42,9 +43,13 @@ typedef struct {
   int hybrid;       /* ORC_HYB_*                                               */
   int bc[6];        /* x-, x+, y-, y+, z-, z+ : ORC_BC_*                       */
   double thr_L[3];  /* characteristic length L per direction in Eq.(35)       */
+  const double *inflow; /* ORC_BC_INFLOW on bc[0]: the conserved state of the
+                           ghosts left of x line y, inflow[v*ny + y]; else
+                           unused (Sec. 4.7, the jet's left boundary)      */
 } orc_params;
 
-/* Fill defaults for a grid: thr_L[d] = n_d * dx, transmissive boundaries. */
+/* Fill defaults for a grid: thr_L[d] = n_d * dx, transmissive boundaries,
+ * inflow = NULL. */
 int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx);
 
 /* Scalar WENO-L2IS reconstruction at x_{j+1/2} from a[0..4] = f_{j-2..j+2}
@@ -101,7 +106,8 @@ int orc_cfl_dt(const double *U, int nx, int ny, int nz, double dx,
                double gamma, double cfl, double *dt);
 
 /* One third-order SSP Runge-Kutta step in place.  dt_in > 0: use it;
- * otherwise the CFL dt of the current state.  dt_used may be NULL. */
+ * otherwise the CFL dt of the current state, whose maximum speed also takes
+ * the inflow ghost states of an ORC_BC_INFLOW side.  dt_used may be NULL. */
 int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
              const orc_params *p, double dt_in, double *dt_used);
 

@@ -23,7 +23,7 @@ DEFAULT_LIB = os.path.join(HERE, "liboracle_l2is.so")  # what build() writes
 LIB_PATH = os.environ.get("ORACLE_L2IS_LIB") or DEFAULT_LIB  # what lib() loads
 SOURCES = ["weno_scalar.c", "charsys.c", "face.c", "solver.c"]
 
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
 
@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("hybrid", C.c_int),
         ("bc", C.c_int * 6),
         ("thr_L", C.c_double * 3),
+        ("inflow", C.POINTER(C.c_double)),
     ]
 
 
@@ -107,6 +108,12 @@ def params(nx: int, ny: int, nz: int, dx: float, **kw) -> Params:
         elif k == "thr_L":
             for i, b in enumerate(v):
                 p.thr_L[i] = float(b)
+        elif k == "inflow":
+            # conserved ghost state [nvar][ny*nz] of the x- inflow side; the
+            # array is kept alive with the structure
+            arr = np.ascontiguousarray(v, dtype=np.float64).ravel()
+            p._inflow_keep = arr
+            p.inflow = arr.ctypes.data_as(C.POINTER(C.c_double))
         else:
             setattr(p, k, v)
     return p

@@ -7,7 +7,9 @@
  *
  * Boundary ghosts (three layers per side, the paper names the conditions
  * only): periodic = wrap; transmissive = copy of the boundary cell;
- * reflective = mirror image of the interior with the normal momentum negated.
+ * reflective = mirror image of the interior with the normal momentum negated;
+ * inflow (x- side of a 1D/2D grid, Sec. 4.7) = the prescribed state of the
+ * x line, the same in all three ghosts.
  * The switch threshold of Eq.(35) uses L = thr_L[d] for direction d.
  * The time step is dt = cfl * dx / max_cells sum_d (|u_d| + c).
  */
@@ -37,7 +39,8 @@ static int check_params(const grid_t *g, const orc_params *p) {
   int d;
   for (d = 0; d < g->dim; ++d) {
     int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return -1;
+    if (lo < 0 || lo > 3 || hi < 0 || hi > 2) return -1;
+    if (lo == ORC_BC_INFLOW && (d != 0 || g->dim == 3 || !p->inflow)) return -1;
     if ((lo == ORC_BC_PERIODIC) != (hi == ORC_BC_PERIODIC)) return -1;
     if ((lo == ORC_BC_REFLECTIVE || hi == ORC_BC_REFLECTIVE) && g->n[d] < 3) return -1;
     if (!(p->thr_L[d] > 0.0)) return -1;
@@ -56,6 +59,7 @@ int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx) {
   p->split = ORC_SPLIT_LLF;
   p->hybrid = ORC_HYB_PER_FIELD;
   for (d = 0; d < 6; ++d) p->bc[d] = ORC_BC_TRANSMISSIVE;
+  p->inflow = 0;
   p->thr_L[0] = nx * dx;
   p->thr_L[1] = ny * dx;
   p->thr_L[2] = nz * dx;
@@ -82,6 +86,7 @@ static int ghost_map(int k, int n, int bclo, int bchi, int *flip) {
   if (k < 0) {
     if (bclo == ORC_BC_PERIODIC) return ((k % n) + n) % n;
     if (bclo == ORC_BC_TRANSMISSIVE) return 0;
+    if (bclo == ORC_BC_INFLOW) return -1; /* no interior source */
     *flip = 1;
     return -1 - k;
   }
@@ -91,24 +96,30 @@ static int ghost_map(int k, int n, int bclo, int bchi, int *flip) {
   return 2 * n - 1 - k;
 }
 
+/* Component v of the state at cell idx of the line along d whose position
+ * along d is k (a ghost when outside 0..n-1), boundary rules applied. */
+static double cell_value(const grid_t *g, const orc_params *p, const double *U,
+                         int d, int v, int k, const int idx[3]) {
+  int flip, src = ghost_map(k, g->n[d], p->bc[2 * d], p->bc[2 * d + 1], &flip);
+  int i[3];
+  double val;
+  if (src < 0) /* inflow ghost: the state given for this x line */
+    return p->inflow[(long long)v * g->n[1] * g->n[2] + idx[1] + (long long)g->n[1] * idx[2]];
+  i[0] = idx[0];
+  i[1] = idx[1];
+  i[2] = idx[2];
+  i[d] = src;
+  val = U[at(g, v, i[0], i[1], i[2])];
+  return (flip && v == 1 + d) ? -val : val;
+}
+
 /* Gather the line through (c0,c1,c2) along d, with 3 ghosts per side,
  * into buf[(k+3)*nvar + v], k = -3..n+2. */
 static void gather_line(const grid_t *g, const orc_params *p, const double *U,
                         int d, const int cidx[3], double *buf) {
   int n = g->n[d], k, v;
-  for (k = -3; k < n + 3; ++k) {
-    int flip, src = ghost_map(k, n, p->bc[2 * d], p->bc[2 * d + 1], &flip);
-    int idx[3];
-    idx[0] = cidx[0];
-    idx[1] = cidx[1];
-    idx[2] = cidx[2];
-    idx[d] = src;
-    for (v = 0; v < g->nvar; ++v) {
-      double val = U[at(g, v, idx[0], idx[1], idx[2])];
-      if (flip && v == 1 + d) val = -val;
-      buf[(k + 3) * g->nvar + v] = val;
-    }
-  }
+  for (k = -3; k < n + 3; ++k)
+    for (v = 0; v < g->nvar; ++v) buf[(k + 3) * g->nvar + v] = cell_value(g, p, U, d, v, k, cidx);
 }
 
 /* Global LF speeds per field along d: max over cells of |lambda^s(U)|. */
@@ -224,20 +235,11 @@ int orc_rhs_at(const double *U, int nx, int ny, int nz, double dx,
     for (v = 0; v < g.nvar; ++v) out[v * ncells + q] = 0.0;
     for (d = 0; d < g.dim; ++d) {
       /* cells i-3 .. i+3 around the target along d, ghosts applied */
-      int n = g.n[d], k;
+      int k;
       double eps_thr = threshold(p, dx, d);
-      for (k = -3; k <= 3; ++k) {
-        int flip, idx[3];
-        idx[0] = ci[0];
-        idx[1] = ci[1];
-        idx[2] = ci[2];
-        idx[d] = ghost_map(ci[d] + k, n, p->bc[2 * d], p->bc[2 * d + 1], &flip);
-        for (v = 0; v < g.nvar; ++v) {
-          double val = U[at(&g, v, idx[0], idx[1], idx[2])];
-          if (flip && v == 1 + d) val = -val;
-          buf[(k + 3) * g.nvar + v] = val;
-        }
-      }
+      for (k = -3; k <= 3; ++k)
+        for (v = 0; v < g.nvar; ++v)
+          buf[(k + 3) * g.nvar + v] = cell_value(&g, p, U, d, v, ci[d] + k, ci);
       /* face i-1/2 uses cells i-3..i+2, face i+1/2 uses i-2..i+3 */
       rc = orc_face_flux(g.nvar, d, gamma, p, eps_thr, alpha_lf[d], buf, Fl, 0, 0);
       if (rc) return rc;
@@ -318,24 +320,57 @@ static int nonphysical(const grid_t *g, const double *U, double gamma, long long
   return !(pr > 0.0);
 }
 
+/* max over the cells of sum_d (|u_d| + c) (NaN if a cell gives NaN);
+ * *bad set when a cell is non-physical. */
+static double interior_speed(const grid_t *g, const double *U, double gamma, int *bad) {
+  long long c;
+  int v, d;
+  double smax = 0.0, u[5], F[5], prim[7];
+  *bad = 0;
+  for (c = 0; c < g->ncell; ++c) {
+    double s = 0.0;
+    if (nonphysical(g, U, gamma, c)) *bad = 1;
+    for (v = 0; v < g->nvar; ++v) u[v] = U[v * g->ncell + c];
+    orc_phys_flux(g->nvar, 0, gamma, u, F, prim);
+    for (d = 0; d < g->dim; ++d) s += fabs(prim[1 + d]) + prim[5];
+    if (s > smax || s != s) smax = s;
+  }
+  return smax;
+}
+
 int orc_cfl_dt(const double *U, int nx, int ny, int nz, double dx,
                double gamma, double cfl, double *dt) {
   grid_t g;
-  long long c;
-  int v, d, bad = 0;
-  double smax = 0.0, u[5], F[5], prim[7];
+  int bad;
+  double smax;
   if (!U || !dt || !(dx > 0.0) || !(gamma > 1.0) || !(cfl > 0.0)) return -1;
   if (grid_init(&g, nx, ny, nz)) return -1;
-  for (c = 0; c < g.ncell; ++c) {
-    double s = 0.0;
-    if (nonphysical(&g, U, gamma, c)) bad = 1;
-    for (v = 0; v < g.nvar; ++v) u[v] = U[v * g.ncell + c];
-    orc_phys_flux(g.nvar, 0, gamma, u, F, prim);
-    for (d = 0; d < g.dim; ++d) s += fabs(prim[1 + d]) + prim[5];
-    if (s > smax || s != s) smax = s;
-  }
+  smax = interior_speed(&g, U, gamma, &bad);
   *dt = cfl * dx / smax;
   return bad;
+}
+
+/* Time step of the scheme: the CFL step of the interior, with the speed of
+ * the inflow ghost states included when the x- side is an inflow (the jet
+ * enters at its own speed, which no interior cell has at the start). */
+static int scheme_dt(const double *U, const grid_t *g, double dx, double gamma,
+                     const orc_params *p, double *dt) {
+  int st;
+  double smax = interior_speed(g, U, gamma, &st);
+  if (p->bc[0] == ORC_BC_INFLOW) {
+    long long rows = (long long)g->n[1] * g->n[2], r;
+    double u[5], F[5], prim[7];
+    int v, d;
+    for (r = 0; r < rows; ++r) {
+      double s = 0.0;
+      for (v = 0; v < g->nvar; ++v) u[v] = p->inflow[v * rows + r];
+      orc_phys_flux(g->nvar, 0, gamma, u, F, prim);
+      for (d = 0; d < g->dim; ++d) s += fabs(prim[1 + d]) + prim[5];
+      if (s > smax) smax = s;
+    }
+  }
+  *dt = p->cfl * dx / smax;
+  return st;
 }
 
 int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
@@ -350,7 +385,7 @@ int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
   if (dt_in > 0.0) {
     dt = dt_in;
   } else {
-    st = orc_cfl_dt(U, nx, ny, nz, dx, gamma, p->cfl, &dt);
+    st = scheme_dt(U, &g, dx, gamma, p, &dt);
     if (st < 0) return st;
   }
   if (dt_used) *dt_used = dt;
@@ -385,8 +420,11 @@ int orc_run(double *U, int nx, int ny, int nz, double dx, double gamma,
             int *steps_out) {
   double t = 0.0, dt;
   int steps = 0, st = 0;
+  grid_t g;
+  if (!U || !p || !(dx > 0.0) || !(gamma > 1.0)) return -1;
+  if (grid_init(&g, nx, ny, nz) || check_params(&g, p)) return -1;
   while (t < t_end && steps < max_steps) {
-    st = orc_cfl_dt(U, nx, ny, nz, dx, gamma, p->cfl, &dt);
+    st = scheme_dt(U, &g, dx, gamma, p, &dt);
     if (st) break;
     if (t + dt > t_end) dt = t_end - t;
     st = orc_step(U, nx, ny, nz, dx, gamma, p, dt, 0);

@@ -18,7 +18,7 @@ LIB_PATH = _build.LIB
 
 OK, E_NULL, E_SHAPE, E_PARAM, E_BC, E_HIP, E_NOMEM, E_BUDGET, E_SLOT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 S_NONPHYSICAL = 1
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
 PATH_AUTO, PATH_SWEEPS, PATH_FUSED, PATH_FUSED_CELLS = 0, 1, 2, 3
@@ -62,6 +62,7 @@ def lib():
         "weno_l2is_step": (ip, [vp, vp, dp]),
         "weno_l2is_advance": (ip, [vp, vp, ip, dp]),
         "weno_l2is_set_time": (ip, [vp, dp]),
+        "weno_l2is_set_inflow": (ip, [vp, vp]),
         "weno_l2is_cfl_dt": (ip, [vp, vp, C.POINTER(dp)]),
         "weno_l2is_time": (ip, [vp, C.POINTER(dp), C.POINTER(dp), C.POINTER(C.c_uint)]),
         "weno_l2is_face_debug": (ip, [vp, vp, ip, vp, vp]),
@@ -162,6 +163,11 @@ class Context:
 
     def advance(self, U, n_steps: int, t_end: float):
         _chk(lib().weno_l2is_advance(self.h, self._u(U), int(n_steps), float(t_end)), "advance")
+
+    def set_inflow(self, state):
+        """Ghost state of the x- inflow side: conserved [nvar][ny*nz] (device)."""
+        _chk(lib().weno_l2is_set_inflow(self.h, _ptr(state, self.nvar * self.shape[1] * self.shape[2])),
+             "set_inflow")
 
     def set_time(self, t: float):
         _chk(lib().weno_l2is_set_time(self.h, float(t)), "set_time")

@@ -52,9 +52,12 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
 // use_clock (dt = 0, a no-op step, once the clock has reached t_end or a
 // non-physical state was seen); resets the running maximum for the next
 // reduction.  Launched as one wavefront.
-[[maybe_unused]] static __global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock) {
+[[maybe_unused]] static __global__ void finalize_dt_kernel(StepCtl* ctl, double cfl_dx, double dt_fixed, int use_clock,
+                                          double s_floor) {
   if (blockIdx.x != 0 || threadIdx.x >= 64) return;
-  const double smax = cfl_take_wave(ctl);  // also resets it for the next reduction
+  double smax = cfl_take_wave(ctl);  // also resets it for the next reduction
+  // speeds that enter through an inflow side (a NaN maximum stays NaN)
+  if (s_floor > smax) smax = s_floor;
   if (threadIdx.x != 0) return;
   double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / smax;
   if (use_clock) {

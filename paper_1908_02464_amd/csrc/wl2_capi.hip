@@ -37,6 +37,9 @@ struct weno_l2is_ctx {
   unsigned int* fo_map = nullptr;  // and the cell -> list entry map (null: per-cell kernel)
   double* fo3 = nullptr;           // 3D, every face WENO: each face's change (face-once)
   unsigned int* counts = nullptr;  // 3D: entries each stage-kernel workgroup listed
+  double* inflow = nullptr;        // x- inflow side: ghost state [nvar][ny*nz]
+  bool inflow_set = false;         // weno_l2is_set_inflow has been called
+  double inflow_speed = 0.0;       // CFL speed sum_d(|u_d| + c), max over the inflow states
   StepCtl* ctl;
   KGrid g;
   KPhys ph;
@@ -109,7 +112,15 @@ int validate(int nx, int ny, int nz, double dx, double gamma, const weno_l2is_pa
   return validate_grid(nx, ny, nz, dx, gamma, p);
 }
 
-void fill_desc(weno_l2is_ctx* c) { fill_grid_desc(c->n, c->dim, c->dx, c->gamma, c->p, c->g, c->ph); }
+void fill_desc(weno_l2is_ctx* c) {
+  fill_grid_desc(c->n, c->dim, c->dx, c->gamma, c->p, c->g, c->ph);
+  c->g.inflow = c->inflow;
+}
+
+// An inflow side whose ghost state has not been given yet.
+bool inflow_missing(const weno_l2is_ctx* c) {
+  return c->p.bc[0] == WL2_BC_INFLOW && !c->inflow_set;
+}
 
 int hip_err(hipError_t e) { return e == hipSuccess ? WL2_OK : WL2_E_HIP; }
 
@@ -175,7 +186,7 @@ hipError_t launch_cfl(const weno_l2is_ctx* c, const double* U, double dt_fixed, 
   {
     TimedLaunch tl(c, "finalize_dt");
     hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, c->p.cfl * c->dx,
-                       dt_fixed, use_clock);
+                       dt_fixed, use_clock, c->inflow_speed);
   }
   return hipGetLastError();
 }
@@ -196,6 +207,7 @@ bool use_row(const weno_l2is_ctx* c) { return c->dim <= 2 && c->path != WL2_PATH
 // advance() of a small 1D grid runs in one single-workgroup launch (not with
 // global Lax-Friedrichs speeds, which need a grid-wide reduction per stage)
 bool use_row_steps(const weno_l2is_ctx* c) {
+  if (c->p.bc[0] == WL2_BC_INFLOW) return false;  // its time step has no inflow speed
   return c->dim == 1 && use_row(c) && c->n[0] <= ROW_STEPS_MAX_CELLS && c->p.split != WL2_SPLIT_LF;
 }
 
@@ -429,6 +441,9 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   if (ok && c->dim == 3 && p->hybrid == WL2_HYB_WENO_ONLY && p->split == WL2_SPLIT_LLF)
     ok = hipMalloc(&c->fo3, sizeof(double) * fused3d_face_doubles(c->n)) == hipSuccess;
   // 3D: per-workgroup counts of the correction list and their prefix sums
+  if (ok && p->bc[0] == WL2_BC_INFLOW)
+    ok = hipMalloc(&c->inflow, sizeof(double) * c->nvar * (size_t)ny * nz) == hipSuccess;
+  if (ok) c->g.inflow = c->inflow;
   if (ok && c->dim == 3)
     ok = hipMalloc(&c->counts, sizeof(unsigned int) * (2 * fused3d_count_entries(c->n) + 1)) ==
          hipSuccess;
@@ -442,6 +457,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
     (void)hipFree(c->fo_map);
     (void)hipFree(c->fo3);
     (void)hipFree(c->counts);
+    (void)hipFree(c->inflow);
     (void)hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
@@ -463,13 +479,47 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   (void)hipFree(c->fo_map);
   (void)hipFree(c->fo3);
   (void)hipFree(c->counts);
+  (void)hipFree(c->inflow);
   (void)hipFree(c->ctl);
   delete c;
+}
+
+int weno_l2is_set_inflow(weno_l2is_ctx* c, const double* state) {
+  if (!c || !state) return WL2_E_NULL;
+  if (c->p.bc[0] != WL2_BC_INFLOW || !c->inflow) return WL2_E_BC;
+  const size_t bytes = sizeof(double) * c->nvar * (size_t)c->n[1] * c->n[2];
+  hipError_t e = hipMemcpyAsync(c->inflow, state, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  // the time step also bounds the speed of the inflow states (the jet enters
+  // at a speed no interior cell has yet): their CFL speed, on the host
+  std::vector<double> h((size_t)c->nvar * c->n[1] * c->n[2]);
+  if (e == hipSuccess) e = hipMemcpy(h.data(), c->inflow, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return WL2_E_HIP;
+  const size_t rows = (size_t)c->n[1] * c->n[2];
+  double smax = 0.0;
+  for (size_t r = 0; r < rows; ++r) {
+    const double rho = h[r], E = h[(c->nvar - 1) * rows + r];
+    double q = 0.0;
+    for (int d = 0; d < c->dim; ++d) {
+      const double u = h[(1 + d) * rows + r] / rho;
+      q += u * u;
+    }
+    const double p = (c->gamma - 1.0) * (E - 0.5 * rho * q);
+    if (!(rho > 0.0) || !(p > 0.0) || !std::isfinite(E)) return WL2_E_PARAM;
+    const double cs = std::sqrt(c->gamma * p / rho);
+    double s = 0.0;
+    for (int d = 0; d < c->dim; ++d) s += std::fabs(h[(1 + d) * rows + r] / rho) + cs;
+    if (s > smax) smax = s;
+  }
+  c->inflow_speed = smax;
+  c->inflow_set = true;
+  return WL2_OK;
 }
 
 int weno_l2is_rhs_ctx(weno_l2is_ctx* c, const double* U, double* dUdt) {
   if (!c || !U || !dUdt) return WL2_E_NULL;
   if (overlaps(U, dUdt, (size_t)c->nvar * c->ncell)) return WL2_E_PARAM;
+  if (inflow_missing(c)) return WL2_E_BC;
   return hip_err(rhs_into(c, U, dUdt));
 }
 
@@ -478,6 +528,7 @@ int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gam
   if (!U || !dUdt) return WL2_E_NULL;
   int rc = validate(nx, ny, nz, dx, gamma, params);
   if (rc) return rc;
+  if (params->bc[0] == WL2_BC_INFLOW) return WL2_E_BC;  // no context to hold its state
   const size_t nc = (size_t)nx * ny * nz;
   if (overlaps(U, dUdt, (size_t)(2 + (ny > 1) + (nz > 1)) * nc)) return WL2_E_PARAM;
   int dev = 0;
@@ -503,6 +554,7 @@ int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gam
 int weno_l2is_step(weno_l2is_ctx* c, double* U, double dt) {
   if (!c || !U) return WL2_E_NULL;
   if (dt > 0.0 && !std::isfinite(dt)) return WL2_E_PARAM;
+  if (inflow_missing(c)) return WL2_E_BC;
   hipError_t e = launch_cfl(c, U, dt > 0.0 ? dt : 0.0, 0);
   if (e == hipSuccess) e = rk3(c, U);
   return hip_err(e);
@@ -511,6 +563,7 @@ int weno_l2is_step(weno_l2is_ctx* c, double* U, double dt) {
 int weno_l2is_advance(weno_l2is_ctx* c, double* U, int n_steps, double t_end) {
   if (!c || !U) return WL2_E_NULL;
   if (n_steps < 0 || !(t_end > 0.0) || !std::isfinite(t_end)) return WL2_E_PARAM;
+  if (inflow_missing(c)) return WL2_E_BC;
   hipLaunchKernelGGL(set_t_end_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t_end);
   hipError_t e = hipGetLastError();
   // small 1D grids: every step in one single-workgroup launch
@@ -574,6 +627,7 @@ int weno_l2is_face_debug(weno_l2is_ctx* c, const double* U, int dir, unsigned ch
                          double* sigma) {
   if (!c || !U || !flags || !sigma) return WL2_E_NULL;
   if (dir < 0 || dir >= c->dim) return WL2_E_PARAM;
+  if (inflow_missing(c)) return WL2_E_BC;
   long long nface = c->ncell / c->n[dir] * (c->n[dir] + 1);
   const size_t nout = (size_t)c->nvar * (size_t)nface, ubytes = sizeof(double) * c->nvar * (size_t)c->ncell;
   if (overlaps(U, ubytes, flags, nout) || overlaps(U, ubytes, sigma, nout * sizeof(double)) ||

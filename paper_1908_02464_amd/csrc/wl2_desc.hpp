@@ -19,6 +19,7 @@ inline void fill_grid_desc(const int n[3], int dim, double dx, double gamma,
   g.stride[1] = n[0];
   g.stride[2] = (long long)n[0] * n[1];
   g.ncell = (long long)n[0] * n[1] * n[2];
+  g.inflow = nullptr;  // set by the owner of the inflow state
   ph.gamma = gamma;
   ph.gm1 = gamma - 1.0;
   ph.dx = dx;
@@ -53,7 +54,9 @@ inline int validate_grid(int nx, int ny, int nz, double dx, double gamma,
   const int n[3] = {nx, ny, nz};
   for (int d = 0; d < dim; ++d) {
     const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return WL2_E_BC;
+    if (lo < 0 || lo > 3 || hi < 0 || hi > 2) return WL2_E_BC;
+    // inflow: the x- side of a 1D or 2D grid only
+    if (lo == WL2_BC_INFLOW && (d != 0 || dim == 3)) return WL2_E_BC;
     if ((lo == WL2_BC_PERIODIC) != (hi == WL2_BC_PERIODIC)) return WL2_E_BC;
     if ((lo == WL2_BC_REFLECTIVE || hi == WL2_BC_REFLECTIVE) && n[d] < 3) return WL2_E_BC;
     if (!(p->thr_L[d] > 0.0)) return WL2_E_PARAM;

@@ -27,7 +27,7 @@
 
 namespace wl2 {
 
-enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
 enum { SPLIT_LLF = 0, SPLIT_LF = 1, SPLIT_ROE = 2 };
 enum { HYB_PER_FIELD = 0, HYB_PER_FACE = 1, HYB_WENO_ONLY = 2, HYB_LINEAR_ONLY = 3 };
 // What a stage kernel does with the face-flux difference dU of Eq.(19):
@@ -40,6 +40,9 @@ struct KGrid {
   long long stride[3]; // element stride of one step along x, y, z
   long long ncell;     // nx*ny*nz, the stride between variables
   int bc_lo[3], bc_hi[3];
+  // x- inflow side: the conserved state of the three ghosts of each x line,
+  // [nvar][ny*nz] (null for every other boundary rule)
+  const double* inflow;
 };
 
 // Physical and scheme constants passed by value.
@@ -182,7 +185,9 @@ __device__ __forceinline__ int ghost_index(int k, int n, int lo, int hi, bool& f
   if (k >= 0 && k < n) return k;
   if (k < 0) {
     if (lo == BC_PERIODIC) { int r = k % n; return r < 0 ? r + n : r; }
-    if (lo == BC_TRANSMISSIVE) return 0;
+    // inflow ghosts are taken from KGrid::inflow by the caller; the index
+    // returned is an in-grid one
+    if (lo == BC_TRANSMISSIVE || lo == BC_INFLOW) return 0;
     flip = true;
     return -1 - k;
   }
@@ -190,6 +195,14 @@ __device__ __forceinline__ int ghost_index(int k, int n, int lo, int hi, bool& f
   if (hi == BC_TRANSMISSIVE) return n - 1;
   flip = true;
   return 2 * n - 1 - k;
+}
+
+// Ghost state of the x- inflow side for x line `row` (= y + ny*z).
+template <int NV>
+__device__ __forceinline__ void load_inflow(const KGrid& g, long long row, double (&u)[NV]) {
+  const long long rows = (long long)g.n[1] * g.n[2];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = g.inflow[v * rows + row];
 }
 
 // Load the conserved state at line position k along DIR of the line whose
@@ -203,6 +216,8 @@ __device__ __forceinline__ void load_state(const double* __restrict__ U, const K
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
   if (flip) u[1 + DIR] = -u[1 + DIR];
+  // x lines start at cell offset row * nx
+  if (DIR == 0 && k < 0 && g.bc_lo[0] == BC_INFLOW) load_inflow<NV>(g, base / g.n[0], u);
 }
 
 // ---------------------------------------------------------------- cells

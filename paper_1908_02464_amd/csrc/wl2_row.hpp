@@ -159,6 +159,8 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
   const int hslot = lane < 3 ? lane : RW + lane;
   bool fxh = false;
   const int hx = halo ? ghost_clamped(x0 - 3 + hslot, g.n[0], g.bc_lo[0], g.bc_hi[0], fxh) : 0;
+  // halo ghost of an inflow side: its state comes from g.inflow
+  const bool hin = halo && x0 - 3 + hslot < 0 && g.bc_lo[0] == BC_INFLOW;
   const long long oxy = cx;  // row 0 element offset of the column (x stride 1)
   const long long hxy = hx;
   double cfl_max = 0.0;  // CFL speed of the cells written here (a.cfl set)
@@ -176,6 +178,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
       double hu[NV];
       row_load_raw<NV>(a.Uk, g, hxy, 0, hu);
       row_flip<NV>(g, fxh, 0, hu);
+      if (hin) load_inflow<NV>(g, 0, hu);
       LRec<NV> hr;
       make_lrec<NV>(hu, ph, hr);
       row_put<NV>(buf, hslot, hr);
@@ -258,6 +261,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
       row_put<NV>(buf, lane + 3, r0);  // cell (x, y)
       if (halo) {
         row_flip<NV>(g, fxh, y, hpre);
+        if (hin) load_inflow<NV>(g, y, hpre);
         LRec<NV> hr;
         make_lrec<NV>(hpre, ph, hr);
         row_put<NV>(buf, hslot, hr);

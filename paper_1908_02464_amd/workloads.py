@@ -84,6 +84,27 @@ def blast_waves(n=400, gamma=GAMMA):
     return conserved(np.ones(n), [np.zeros(n)], p, gamma).reshape(3, 1, 1, n), dx
 
 
+JET_GAMMA = 5.0 / 3.0
+
+
+def mach2000_jet(nx=640, ny=160, gamma=JET_GAMMA):
+    """Mach 2000 jet (Sec. 4.7) on [0,1] x [0,0.25]: ambient gas
+    (rho, u, v, p) = (0.5, 0, 0, 0.4127) everywhere; the left side is an
+    inflow whose ghosts hold the jet (5, 800, 0, 0.4127) for y < 0.05 and
+    the ambient state above; reflective bottom, outflow right and top;
+    gamma = 5/3, CFL 0.25, t_end = 0.001.  Returns (U0, dx, inflow), inflow
+    the conserved ghost state [4][ny]."""
+    x, dx = centres(nx, 0.0, 1.0)
+    y, _ = centres(ny, 0.0, 0.25)
+    rho = np.full((ny, nx), 0.5)
+    zero = np.zeros((ny, nx))
+    U0 = conserved(rho, [zero, zero], np.full((ny, nx), 0.4127), gamma).reshape(4, 1, ny, nx)
+    jet = y < 0.05
+    inflow = conserved(np.where(jet, 5.0, 0.5), [np.where(jet, 800.0, 0.0), np.zeros(ny)],
+                       np.full(ny, 0.4127), gamma)
+    return U0, dx, np.ascontiguousarray(inflow.reshape(4, ny))
+
+
 def shu_osher(n=1600, gamma=GAMMA):
     """Mach-3 shock / entropy wave on [-5,5]: shocked state for x < -4."""
     x, dx = centres(n, -5.0, 5.0)

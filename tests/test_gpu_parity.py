@@ -849,3 +849,139 @@ def test_3d_correction_modes_weno_only(orc, capi, shape, bc):
     err = z20(a[0], Uo)
     say(f"    {shape} bc={bc} WENO only: z20 = {err:.3e}")
     assert err <= 1e-12
+
+
+# ---------------------------------------------------------------- inflow side
+def _inflow_case(case):
+    """(U, dx, inflow state) of the inflow cases: random gas with a per-row
+    inflow state (2D), the same in 1D, the jet of Sec. 4.7."""
+    from test_oracle_inflow import _jet_like
+    if case.startswith("rand2d"):
+        nx, ny = (int(s) for s in case[6:].split("x"))
+        U, inf = _jet_like(nx, ny, 11)
+        return U, 0.05, inf, G
+    if case == "rand1d64":
+        U2, inf2 = _jet_like(64, 2, 5)
+        U = np.ascontiguousarray(np.stack([U2[0, 0, 0], U2[1, 0, 0],
+                                           U2[3, 0, 0] - 0.5 * U2[2, 0, 0] ** 2 / U2[0, 0, 0]]).reshape(3, 1, 1, 64))
+        inf = np.array([inf2[0, 0], inf2[1, 0], inf2[3, 0] - 0.5 * inf2[2, 0] ** 2 / inf2[0, 0]]).reshape(3, 1)
+        return U, 0.05, inf, G
+    nx, ny = (int(s) for s in case[3:].split("x"))
+    U, dx, inf = w.mach2000_jet(nx, ny)
+    return U, dx, inf, w.JET_GAMMA
+
+
+def _inflow_ctx(capi, U, dx, inf, gamma, **kw):
+    nx, ny, nz = shape_of(U)
+    bc = [3, 1, 1, 1, 1, 1] if ny == 1 else [3, 1, 2, 1, 1, 1]
+    ctx = capi.Context(nx, ny, nz, dx, gamma, capi.params_default(nx, ny, nz, dx, bc=bc, **kw))
+    ctx.set_inflow(to_dev(inf))
+    return ctx, bc
+
+
+@pytest.mark.parametrize("case,kw,path", [
+    ("rand2d24x16", {}, 0), ("rand2d24x16", {"split": 2}, 0), ("rand2d24x16", {"hybrid": 2}, 0),
+    ("rand2d24x16", {"split": 1}, 0), ("rand2d24x16", {}, 1), ("rand2d512x256", {}, 0),
+    ("rand1d64", {}, 0), ("rand1d64", {"split": 2, "hybrid": 1}, 1), ("jet160x40", {}, 0)])
+def test_inflow_rhs_parity(orc, capi, case, kw, path):
+    """Right-hand side with an inflow side (its ghosts hold the given state
+    of each x line) against the oracle, through the row kernel, the sweep
+    kernels (path 1) and the 2D face-once corrections (512 x 256)."""
+    import torch
+    say(f"[inflow rhs] case={case} kw={kw} path={path}")
+    U, dx, inf, g = _inflow_case(case)
+    ctx, bc = _inflow_ctx(capi, U, dx, inf, g, **kw)
+    if path:
+        ctx.tune(path=path)
+    nx, ny, nz = shape_of(U)
+    po = orc.params(nx, ny, nz, dx, bc=bc, inflow=inf, **kw)
+    ref = orc.rhs(U, dx, g, po)
+    Ud = to_dev(U)
+    out = torch.full_like(Ud, float("nan"))
+    ctx.rhs(Ud, out)
+    torch.cuda.synchronize()
+    got = to_host(out)
+    ctx.close()
+    assert np.all(np.isfinite(got))
+    # the bar of every rhs test (the change within one step, in units of the
+    # state), with the step and the state's scale those of the scheme: the
+    # time step bounds the inflow speed too, and the fluxes at the inflow
+    # side carry the ghost state (the jet's E = 1.6e6 against 0.62 inside)
+    dt, st = orc.step(U.copy(), dx, g, po)
+    assert st == 0
+    err = 0.0
+    for c in range(U.shape[0]):
+        scale = max(float(np.abs(U[c]).max()), float(np.abs(inf[c]).max()), 1e-300)
+        err = max(err, float(np.abs(got[c] - ref[c]).max()) * dt / scale)
+    say(f"    rhs err = {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("case,nsteps", [("rand2d24x16", 100), ("rand1d64", 100),
+                                         ("jet160x40", 30), ("jet640x160", 20)])
+def test_inflow_steps_parity(orc, capi, case, nsteps):
+    """Steps on the device clock with an inflow side: the time step takes the
+    inflow states' speed (the jet's first step is bounded by 800 + 2c, not
+    by the gas at rest), the oracle's dt sequence and state to the bar."""
+    import torch
+    say(f"[inflow steps] case={case} steps={nsteps}")
+    U, dx, inf, g = _inflow_case(case)
+    nx, ny, nz = shape_of(U)
+    kw = {"cfl": 0.25} if case.startswith("jet") else {}
+    ctx, bc = _inflow_ctx(capi, U, dx, inf, g, **kw)
+    po = orc.params(nx, ny, nz, dx, bc=bc, inflow=inf, **kw)
+    Uo = U.copy()
+    t = 0.0
+    for _ in range(nsteps):
+        dt, st = orc.step(Uo, dx, g, po)
+        assert st == 0
+        t += dt
+    Ud = to_dev(U)
+    ctx.set_time(0.0)
+    ctx.advance(Ud, nsteps, 1e30)  # a clock target that is never reached
+    tg, _, k = ctx.clock()
+    stg = ctx.status()
+    ctx.close()
+    torch.cuda.synchronize()
+    got = to_host(Ud).reshape(U.shape)
+    err = z20(got, Uo)
+    say(f"    t oracle={t:.6e} gpu={tg:.6e} z20={err:.3e}")
+    assert stg == 0 and k == nsteps and abs(tg - t) <= 1e-12 * t
+    assert err <= 1e-10
+
+
+def test_inflow_refusals(capi):
+    """Inflow misplaced, its state missing or non-physical: refused."""
+    import ctypes as C
+    import torch
+    say("[inflow errors]")
+    L = capi.lib()
+    h = C.c_void_p()
+    for shape, bc in [((8, 8, 8), [3, 1, 1, 1, 1, 1]), ((8, 8, 1), [1, 3, 1, 1, 1, 1]),
+                      ((8, 8, 1), [1, 1, 3, 1, 1, 1])]:
+        p = capi.params_default(*shape, 0.1, bc=bc)
+        assert L.weno_l2is_create(*shape, 0.1, G, C.byref(p), None, C.byref(h)) == -4
+    U = to_dev(np.ascontiguousarray(np.stack([np.ones((8, 8)), np.zeros((8, 8)), np.zeros((8, 8)),
+                                              np.full((8, 8), 2.5)]).reshape(4, 1, 8, 8)))
+    out = torch.empty_like(U)
+    p = capi.params_default(8, 8, 1, 0.1, bc=[3, 1, 1, 1, 1, 1])
+    assert L.weno_l2is_rhs(U.data_ptr(), 8, 8, 1, 0.1, G, C.byref(p), out.data_ptr()) == -4
+    ctx = capi.Context(8, 8, 1, 0.1, G, p)
+    assert L.weno_l2is_step(ctx.h, U.data_ptr(), -1.0) == -4  # no state yet
+    assert L.weno_l2is_rhs_ctx(ctx.h, U.data_ptr(), out.data_ptr()) == -4
+    assert L.weno_l2is_advance(ctx.h, U.data_ptr(), 1, 1.0) == -4
+    bad = to_dev(np.ones((4, 8)) * np.array([[-1.0], [0.0], [0.0], [2.5]]))
+    assert L.weno_l2is_set_inflow(ctx.h, bad.data_ptr()) == -3
+    good = to_dev(np.ones((4, 8)) * np.array([[1.0], [0.5], [0.0], [2.5]]))
+    assert L.weno_l2is_set_inflow(ctx.h, good.data_ptr()) == 0
+    assert L.weno_l2is_rhs_ctx(ctx.h, U.data_ptr(), out.data_ptr()) == 0
+    ctx.close()
+    plain = capi.Context(8, 8, 1, 0.1, G)
+    assert L.weno_l2is_set_inflow(plain.h, good.data_ptr()) == -4
+    plain.close()
+    b = capi.Batch(1 << 24)
+    slot, nbytes = C.c_int(-1), C.c_size_t(0)
+    assert L.weno_l2is_batch_admit(b.h, 8, 8, 1, 0.1, G, C.byref(p), U.data_ptr(), 0, 1.0,
+                                   C.byref(slot), C.byref(nbytes)) == -4
+    b.close()
+    torch.cuda.synchronize()
