@@ -83,9 +83,17 @@ def test_eigensystem_and_roe_property(orc, nvar, d):
         # Roe density is the geometric mean
         assert abs(roe[0] - np.sqrt(UL[0] * UR[0])) <= 1e-15 * roe[0]
         # every characteristic variable carries density units: scaling the
-        # state by s (rho -> s rho at fixed velocity and sound speed) scales
-        # L.U by s
-        assert np.all(np.isfinite(L))
+        # mass unit (rho, p, E by s at fixed velocity and sound speed) scales
+        # L.U by s; scaling the time unit (velocities and c by k) leaves it
+        X = rand_state(rng, nvar)
+        s = 2.5
+        Ls = orc.roe_eigen(nvar, d, GAMMA, s * UL, s * UR)[0]
+        np.testing.assert_allclose(Ls @ (s * X), s * (L @ X), rtol=1e-12,
+                                   atol=1e-12 * np.abs(L @ X).max())
+        k = np.array([1.0] + [3.0] * (nvar - 2) + [9.0])
+        Lk = orc.roe_eigen(nvar, d, GAMMA, k * UL, k * UR)[0]
+        np.testing.assert_allclose(Lk @ (k * X), L @ X, rtol=1e-11,
+                                   atol=1e-11 * np.abs(L @ X).max())
 
 
 def poly_stencil(rng, nvar, deg):

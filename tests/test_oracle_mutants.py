@@ -8,8 +8,11 @@ are the kinds of slip the method invites: an index of the mirrored f-
 stencil, a sign of the flux splitting, an L2 error term, a sign inside
 tau5, the Roe density of the detector, a coefficient of the six-point
 central flux, a Runge-Kutta weight, the mirror index of a reflective ghost,
-and weights of another WENO family (inverse-square smoothness weights),
-which lose the fifth order on smooth data.
+weights of another WENO family (inverse-square smoothness weights), which
+lose the fifth order on smooth data, and three readings the paper leaves
+open: shear eigenvectors without the Roe sound speed, the LLF speed over
+the face's two cells instead of its six-cell stencil, and a time step from
+the fastest single direction instead of the sum over directions.
 """
 import os
 import shutil
@@ -20,7 +23,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
-PINS = ["tests/test_oracle_scalar.py", "tests/test_oracle_face.py", "tests/test_oracle_solutions.py"]
+PINS = ["tests/test_oracle_scalar.py", "tests/test_oracle_face.py", "tests/test_oracle_readings.py",
+        "tests/test_oracle_solutions.py"]
 
 # (name, file, text as written, planted mistake)
 MUTANTS = [
@@ -44,6 +48,25 @@ MUTANTS = [
     ("inverse_square_weights", "weno_scalar.c",
      "alpha[k] = d[k] * (1.0 + lam * tau5 / (lam * beta[k] + E[k] + eps_w));",
      "alpha[k] = d[k] / ((beta[k] + eps_w) * (beta[k] + eps_w));"),
+    # shear eigenvectors without the Roe sound speed: the shear field's
+    # characteristic variable then carries momentum units
+    ("shear_eigenvectors_unscaled", "charsys.c",
+     "    R[(1 + t) * nvar + s] = ct;\n"
+     "    R[(nvar - 1) * nvar + s] = ct * ut[t];\n"
+     "    L[s * nvar + 0] = -ut[t] / ct;\n"
+     "    L[s * nvar + 1 + t] = 1.0 / ct;\n",
+     "    R[(1 + t) * nvar + s] = 1.0;\n"
+     "    R[(nvar - 1) * nvar + s] = ut[t];\n"
+     "    L[s * nvar + 0] = -ut[t];\n"
+     "    L[s * nvar + 1 + t] = 1.0;\n"),
+    # LLF speed over the two cells of the face instead of the six-cell stencil
+    ("llf_two_cells", "face.c",
+     "for (m = 0; m < 6; ++m) {\n        double e = fabs(cell_eig(",
+     "for (m = 2; m < 4; ++m) {\n        double e = fabs(cell_eig("),
+    # time step from the largest single-direction speed instead of the sum
+    ("cfl_max_over_directions", "solver.c",
+     "for (d = 0; d < g->dim; ++d) s += fabs(prim[1 + d]) + prim[5];\n    if (s > smax || s != s)",
+     "for (d = 0; d < g->dim; ++d) s = fmax(s, fabs(prim[1 + d]) + prim[5]);\n    if (s > smax || s != s)"),
 ]
 
 
