@@ -51,38 +51,102 @@ def measured_profile():
         return None, "missing"
 
 
+def host_identity():
+    """CPU model, logical CPUs, CPUs this process may run on, OMP_NUM_THREADS."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(U0, dx, min_seconds=10.0):
-    """The oracle as it stands, one thread, on a 256x256x16 slab of the same
-    initial field (x, y periodic as in the workload; z transmissive)."""
+    """The oracle as it stands on the same 256^3 periodic initial field: one
+    thread for one right-hand side (one RK stage's flux evaluation), then
+    every usable core (OpenMP over the lines of a sweep, the same bits) for
+    whole SSP-RK3 steps until min_seconds have passed."""
     from oracle import pyoracle as orc
-    slab = np.ascontiguousarray(U0[:, :16])
-    nz, ny, nx = slab.shape[1:]
-    p = orc.params(nx, ny, nz, dx, bc=[0, 0, 0, 0, 1, 1], thr_L=[N * dx] * 3)
+    host = host_identity()
+    U = np.ascontiguousarray(U0)
+    nz, ny, nx = U.shape[1:]
+    ncell = nx * ny * nz
+    p = orc.params(nx, ny, nz, dx, bc=[0] * 6)
+    orc.threads(1)
+    t0 = time.perf_counter()
+    orc.rhs(U, dx, GAMMA, p)
+    el1 = time.perf_counter() - t0
+    rate1 = ncell / el1 / 1e6
+    cores = host["usable_cpus"] or 1
+    if host["omp_num_threads"]:
+        cores = min(cores, int(host["omp_num_threads"]))
+    used = orc.threads(cores)
+    V = U.copy()
     steps, t0 = 0, time.perf_counter()
     while True:
-        orc.step(slab, dx, GAMMA, p)
+        orc.step(V, dx, GAMMA, p)
         steps += 1
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
-    value = nx * ny * nz * 3 * steps / el / 1e6
-    return {"value": round(value, 4), "unit": "Mcell-updates/s per RK stage", "cores": 1,
+    value = ncell * 3 * steps / el / 1e6
+    orc.threads(1)
+    return {"value": round(value, 4), "unit": "Mcell-updates/s per RK stage", "cores": used,
             "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of the oracle on a {nx}x{ny}x{nz} slab of the same "
-                      f"256^3 initial field ({el:.1f} s, single thread)"}
+            "sample": f"{steps} SSP-RK3 steps of the oracle on the full {nx}x{ny}x{nz} periodic "
+                      f"initial field with {used} OpenMP threads ({el:.1f} s); single thread: one "
+                      f"right-hand side of the same field ({el1:.1f} s)",
+            "single_thread": {"value": round(rate1, 4), "unit": "Mcell-updates/s per RK stage",
+                              "seconds": round(el1, 2)},
+            "host": host}
 
 
-def variants_3d(torch, capi, U0, dx, steps=10):
+def weno_fractions(torch, ctx, Ud, nvar=5):
+    """Per direction: the fraction of faces with some field on the WENO
+    branch, and the fraction of face-fields on it (flags of the state Ud)."""
+    faces, fields = [], []
+    for d in range(3):
+        nf = N ** 2 * (N + 1)
+        fl = torch.empty(nvar * nf, dtype=torch.uint8, device="cuda")
+        sg = torch.empty(nvar * nf, dtype=torch.float64, device="cuda")
+        ctx.face_debug(Ud, d, fl, sg)
+        f = fl.view(nvar, nf)
+        faces.append(float((f.min(dim=0).values == 0).double().mean().item()))
+        fields.append(float((f == 0).double().mean().item()))
+        del fl, sg
+    torch.cuda.synchronize()
+    return faces, fields
+
+
+def variants_3d(torch, capi, U0, dx, steps=10, developed_at=400):
     """The same 256^3 field with every face on the WENO-L2IS branch (switch
     off) and with every face on the linear branch (switch forced), timed like
     the headline after two warm-up steps: the two ends between which the
-    hybrid scheme's cost lies."""
+    hybrid scheme's cost lies.  Then the hybrid on the developed field: the
+    same initial field advanced on the device for developed_at steps, when
+    shocklets have formed and a few percent of the face-fields take the WENO
+    branch (the nonlinear half of the hot path, Eq.(20)-(28), runs in the
+    correction kernel); timed over the next steps with its WENO fractions."""
     out = {}
-    for name, hyb in (("weno_only", 2), ("linear_only", 3)):
+    for name, hyb in (("weno_only", 2), ("linear_only", 3), ("developed", 0)):
         p = capi.params_default(N, N, N, dx, bc=[0] * 6, hybrid=hyb)
         ctx = capi.Context(N, N, N, dx, GAMMA, p)
         Ud = torch.from_numpy(U0).cuda()
-        ctx.advance(Ud, 2, 1e300)
+        ctx.advance(Ud, developed_at if name == "developed" else 2, 1e300)
+        extra = {}
+        if name == "developed":
+            faces, fields = weno_fractions(torch, ctx, Ud)
+            extra = {"start_step": developed_at, "weno_face_fraction_xyz": [round(f, 5) for f in faces],
+                     "weno_face_field_fraction_xyz": [round(f, 5) for f in fields]}
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ctx.stream)
         ctx.advance(Ud, steps, 1e300)
@@ -96,8 +160,8 @@ def variants_3d(torch, capi, U0, dx, steps=10):
         out[name] = {"steps": steps, "ms_per_step": round(ms / steps, 4),
                      "Mcell_updates_per_s_per_stage": round(N ** 3 * 3 * steps / (ms * 1e-3) / 1e6, 2),
                      "kernel_ms_per_step": {k: round(v[0] / 2, 4) for k, v in kt.items()},
-                     "status": ctx.status()}
-        log(f"[bench]   3D {name}: {out[name]['ms_per_step']} ms/step")
+                     "status": ctx.status(), **extra}
+        log(f"[bench]   3D {name}: {out[name]['ms_per_step']} ms/step {extra}")
         ctx.close()
         del Ud
         torch.cuda.empty_cache()
@@ -250,43 +314,32 @@ def main():
         if prof is not None:
             traffic = prof.get("traffic_bytes_per_launch")
             flops = prof.get("fp64_flops_per_launch")
-    # The stage kernel's busiest unit is the FP64 VALU (HBM runs at about a
-    # quarter of its peak): its roofline is the FP64 vector peak, against the
-    # FP64 operations counted by rocprofv3 for this kernel build (committed
-    # summary, same source hash), over the event-timed launch; the HBM
-    # fraction of its algorithmic bytes is reported beside it.  Without a
-    # current counter summary the HBM roofline is the one reported.
-    hbm = {"achieved_GBs": round(achieved, 1), "peak_GBs": HBM_PEAK_GBS,
-           "frac": round(achieved / HBM_PEAK_GBS, 4),
-           "algorithmic_bytes_per_launch": int(dom_bytes)}
+    # Roofline of the stage kernel: its algorithmic HBM bytes over the
+    # event-timed launch against the 8 TB/s peak (the unit the target is set
+    # in), with the counted HBM traffic of the committed rocprofv3 summary
+    # (same kernel-source hash, else null).  Beside it the FP64 side: the
+    # FP64 operations counted for this build over the same time, against the
+    # FP64 vector peak; the counters count every lane of a wave instruction,
+    # so lanes left idle by partial waves make it an upper bound.
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (round(traffic) if traffic else None), "traffic_source": traffic_src,
+                "algorithmic_bytes_per_launch": int(dom_bytes),
+                "bytes_per_cell_stage": round(dom_bytes / ncell, 2),
+                "avg_launch_ms": round(avg_ms, 4), "launches": dom_n}
     if flops:
         tflops = flops / (avg_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(tflops, 2),
-                    "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tflops / FP64_VECTOR_TFLOPS, 4),
-                    "flops_per_launch": round(flops), "flops_per_cell_stage": round(flops / ncell, 1)}
-    else:
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": hbm["achieved_GBs"],
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm["frac"]}
-    roofline.update({"traffic": (round(traffic) if traffic else None),
-                     "traffic_source": traffic_src, "avg_launch_ms": round(avg_ms, 4),
-                     "launches": dom_n, "hbm": hbm})
+        roofline["fp64_valu"] = {"achieved_TFLOPs": round(tflops, 2), "peak_TFLOPs": FP64_VECTOR_TFLOPS,
+                                 "frac_upper_bound": round(tflops / FP64_VECTOR_TFLOPS, 4),
+                                 "flops_per_launch": round(flops),
+                                 "flops_per_cell_stage": round(flops / ncell, 1)}
     # the method's own bytes per cell-stage: 8/3 state arrays (read U^(k), U^n,
     # write U^(k+1); stage 1 reads only U^n)
     path_bytes = 8.0 / 3.0 * nvar * 8
     path_gbs = value * 1e6 * path_bytes / 1e9
 
     # fraction of faces that took the nonlinear flux in some field (final state)
-    weno_frac = []
-    for d in range(3):
-        nf = ncell // N * (N + 1)
-        fl = torch.empty(nvar * nf, dtype=torch.uint8, device="cuda")
-        sg = torch.empty(nvar * nf, dtype=torch.float64, device="cuda")
-        ctx.face_debug(Ud, d, fl, sg)
-        lin_all = fl.view(nvar, nf).min(dim=0).values
-        weno_frac.append(float((lin_all == 0).double().mean().item()))
-        del fl, sg
-    torch.cuda.synchronize()
+    weno_frac, weno_field_frac = weno_fractions(torch, ctx, Ud)
 
     if args.copy_calibration:
         cp = Ud.clone()  # reads and writes exactly one state array
@@ -353,6 +406,7 @@ def main():
             "hybrid": {0: "per-field", 1: "per-face", 2: "weno-only", 3: "linear-only"}[args.hybrid],
             "kernel_path": {0: "fused stage kernel", 1: "per-direction sweeps"}[args.path],
             "weno_face_fraction_xyz": [round(f, 6) for f in weno_frac],
+            "weno_face_field_fraction_xyz": [round(f, 6) for f in weno_field_frac],
         },
         "roofline": roofline,
         "variants_3d": variants,

@@ -107,10 +107,20 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma,
 
 /* Right-hand side of Eq.(19): dUdt = -sum_d (F_{j+1/2} - F_{j-1/2})_d / dx,
  * for the state U (device).  Stateless form: enqueued on the null stream,
- * asynchronous; an internal context per shape is cached and reused.
- * U and dUdt must not overlap (WL2_E_PARAM if they share a byte). */
+ * asynchronous; an internal context per shape and device is cached and
+ * reused until weno_l2is_rhs_release.  U and dUdt must not overlap
+ * (WL2_E_PARAM if they share a byte). */
 int weno_l2is_rhs(const double *U, int nx, int ny, int nz, double dx,
                   double gamma, const weno_l2is_params *params, double *dUdt);
+
+/* Release every context that weno_l2is_rhs keeps (one per grid shape and
+ * device, about 2.2 GB for a 256^3 grid; they are otherwise held until the
+ * process ends).  Waits for their work to finish, then frees their device
+ * memory; a later weno_l2is_rhs builds its context again.  Must not run
+ * while another thread is inside weno_l2is_rhs on a shape being released
+ * (the cache itself is guarded by a lock).  Returns the number of contexts
+ * released (>= 0), or WL2_E_HIP if a device could not be selected. */
+int weno_l2is_rhs_release(void);
 
 /* The same on a context (its stream and scratch); the same overlap rule. */
 int weno_l2is_rhs_ctx(weno_l2is_ctx *ctx, const double *U, double *dUdt);
@@ -140,8 +150,11 @@ int weno_l2is_advance(weno_l2is_ctx *ctx, double *U, int n_steps,
  * prescribes the state (rho, u, v, p) of its ghosts, one state inside the
  * jet and another outside).  state: DEVICE pointer to the conserved state
  * [nvar][ny] (x fastest layout of one column: element v*ny + y is variable
- * v of the three ghost cells left of row y).  Copied into the context
- * before the call returns; the caller keeps ownership.  The context must
+ * v of the three ghost cells left of row y).  Checked (rho > 0, p > 0,
+ * finite) and copied into the context before the call returns; the caller
+ * keeps ownership.  A refused state (WL2_E_PARAM) changes nothing: the
+ * context keeps the last accepted state and its time-step bound.  The
+ * context must
  * have been created with bc[0] == WL2_BC_INFLOW (else WL2_E_BC); until this
  * call has been made, every call that evaluates the right-hand side
  * (rhs_ctx, step, advance, face_debug) returns WL2_E_BC.  The stateless

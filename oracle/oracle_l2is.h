@@ -111,6 +111,11 @@ int orc_cfl_dt(const double *U, int nx, int ny, int nz, double dx,
 int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
              const orc_params *p, double dt_in, double *dt_used);
 
+/* Threads used for the lines of a direction (built with OpenMP; else 1).
+ * n > 0 sets the count; returns the count in effect.  Results do not depend
+ * on it. */
+int orc_threads(int n);
+
 /* Advance to t_end (last step clipped) or max_steps, whichever first.
  * Returns the status of the last check. */
 int orc_run(double *U, int nx, int ny, int nz, double dx, double gamma,

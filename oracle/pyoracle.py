@@ -29,10 +29,11 @@ HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
 
 
 def build(verbose: bool = False, src_dir: str = HERE, out: str = DEFAULT_LIB) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction):
-    the sources in src_dir (default: these) into the library out."""
+    """Compile the oracle with gcc (no fast-math, no FMA contraction; OpenMP
+    over the lines of a sweep, which changes no result bit): the sources in
+    src_dir (default: these) into the library out."""
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", out]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", out]
     cmd += [os.path.join(src_dir, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
@@ -83,8 +84,15 @@ def lib():
         L.orc_step.argtypes = [dp] + grid + [pp, C.c_double, dp]
         L.orc_run.argtypes = [dp] + grid + [pp, C.c_double, C.c_int, dp,
                                             C.POINTER(C.c_int)]
+        L.orc_threads.argtypes = [C.c_int]
+        L.orc_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Set (n > 0) and return the oracle's thread count."""
+    return int(lib().orc_threads(int(n)))
 
 
 def _dp(a: np.ndarray):

@@ -16,6 +16,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "oracle_l2is.h"
 
 typedef struct {
@@ -167,36 +170,53 @@ static void line_index(const grid_t *g, int d, long long line, int cidx[3]) {
 
 static int add_direction(const grid_t *g, const orc_params *p, double gamma,
                          double dx, int d, const double *U, double *dUdt) {
-  int n = g->n[d], i, v, rc = 0;
-  long long nlines = g->ncell / n, line;
+  int n = g->n[d], rc = 0;
+  long long nlines = g->ncell / n;
   double eps_thr = threshold(p, dx, d), alpha_lf[5];
-  double *buf = (double *)malloc(sizeof(double) * (n + 6) * g->nvar);
-  double *Fl = (double *)malloc(sizeof(double) * (n + 1) * g->nvar);
-  if (!buf || !Fl) {
+  if (p->split == ORC_SPLIT_LF) lf_speeds(g, U, gamma, d, alpha_lf);
+  /* lines are independent (each writes only its own cells), so a build with
+   * OpenMP may hand them to threads: the result does not depend on how many */
+#pragma omp parallel
+  {
+    long long line;
+    int i, v, lrc = 0;
+    double *buf = (double *)malloc(sizeof(double) * (n + 6) * g->nvar);
+    double *Fl = (double *)malloc(sizeof(double) * (n + 1) * g->nvar);
+    if (!buf || !Fl) lrc = -2;
+#pragma omp for schedule(static)
+    for (line = 0; line < nlines; ++line) {
+      int cidx[3];
+      if (lrc) continue;
+      line_index(g, d, line, cidx);
+      gather_line(g, p, U, d, cidx, buf);
+      lrc = line_fluxes(g, p, gamma, eps_thr, alpha_lf, d, buf, Fl, 0, 0);
+      for (i = 0; i < n && !lrc; ++i) {
+        int idx[3];
+        idx[0] = cidx[0];
+        idx[1] = cidx[1];
+        idx[2] = cidx[2];
+        idx[d] = i;
+        for (v = 0; v < g->nvar; ++v)
+          dUdt[at(g, v, idx[0], idx[1], idx[2])] -=
+              (Fl[(i + 1) * g->nvar + v] - Fl[i * g->nvar + v]) / dx;
+      }
+    }
+#pragma omp critical
+    if (lrc && !rc) rc = lrc;
     free(buf);
     free(Fl);
-    return -2;
   }
-  if (p->split == ORC_SPLIT_LF) lf_speeds(g, U, gamma, d, alpha_lf);
-  for (line = 0; line < nlines && !rc; ++line) {
-    int cidx[3];
-    line_index(g, d, line, cidx);
-    gather_line(g, p, U, d, cidx, buf);
-    rc = line_fluxes(g, p, gamma, eps_thr, alpha_lf, d, buf, Fl, 0, 0);
-    for (i = 0; i < n && !rc; ++i) {
-      int idx[3];
-      idx[0] = cidx[0];
-      idx[1] = cidx[1];
-      idx[2] = cidx[2];
-      idx[d] = i;
-      for (v = 0; v < g->nvar; ++v)
-        dUdt[at(g, v, idx[0], idx[1], idx[2])] -=
-            (Fl[(i + 1) * g->nvar + v] - Fl[i * g->nvar + v]) / dx;
-    }
-  }
-  free(buf);
-  free(Fl);
   return rc;
+}
+
+int orc_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 int orc_rhs(const double *U, int nx, int ny, int nz, double dx, double gamma,

@@ -59,6 +59,7 @@ def lib():
         "weno_l2is_create": (ip, [ip, ip, ip, dp, dp, pp, vp, C.POINTER(vp)]),
         "weno_l2is_rhs": (ip, [vp, ip, ip, ip, dp, dp, pp, vp]),
         "weno_l2is_rhs_ctx": (ip, [vp, vp, vp]),
+        "weno_l2is_rhs_release": (ip, []),
         "weno_l2is_step": (ip, [vp, vp, dp]),
         "weno_l2is_advance": (ip, [vp, vp, ip, dp]),
         "weno_l2is_set_time": (ip, [vp, dp]),
@@ -134,6 +135,14 @@ def rhs(U: torch.Tensor, nx: int, ny: int, nz: int, dx: float, gamma: float, par
     _, nvar, ncell = grid_dims(nx, ny, nz)
     _chk(lib().weno_l2is_rhs(_ptr(U, nvar * ncell), nx, ny, nz, dx, gamma, C.byref(params),
                              _ptr(dUdt, nvar * ncell)), "rhs")
+
+
+def rhs_release() -> int:
+    """Free the contexts cached by the stateless rhs (weno_l2is_rhs_release);
+    returns how many were released."""
+    n = lib().weno_l2is_rhs_release()
+    _chk(min(n, 0), "rhs_release")
+    return n
 
 
 class Context:

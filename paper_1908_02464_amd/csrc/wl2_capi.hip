@@ -487,15 +487,17 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
 int weno_l2is_set_inflow(weno_l2is_ctx* c, const double* state) {
   if (!c || !state) return WL2_E_NULL;
   if (c->p.bc[0] != WL2_BC_INFLOW || !c->inflow) return WL2_E_BC;
-  const size_t bytes = sizeof(double) * c->nvar * (size_t)c->n[1] * c->n[2];
-  hipError_t e = hipMemcpyAsync(c->inflow, state, bytes, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  // the time step also bounds the speed of the inflow states (the jet enters
-  // at a speed no interior cell has yet): their CFL speed, on the host
-  std::vector<double> h((size_t)c->nvar * c->n[1] * c->n[2]);
-  if (e == hipSuccess) e = hipMemcpy(h.data(), c->inflow, bytes, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return WL2_E_HIP;
   const size_t rows = (size_t)c->n[1] * c->n[2];
+  const size_t bytes = sizeof(double) * c->nvar * rows;
+  // the caller's state is checked on the host before it replaces anything:
+  // a refused state leaves the ghosts and the inflow speed of the last
+  // accepted one in place
+  std::vector<double> h((size_t)c->nvar * rows);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(h.data(), state, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return WL2_E_HIP;
+  // the time step also bounds the speed of the inflow states (the jet enters
+  // at a speed no interior cell has yet): their CFL speed
   double smax = 0.0;
   for (size_t r = 0; r < rows; ++r) {
     const double rho = h[r], E = h[(c->nvar - 1) * rows + r];
@@ -511,6 +513,9 @@ int weno_l2is_set_inflow(weno_l2is_ctx* c, const double* state) {
     for (int d = 0; d < c->dim; ++d) s += std::fabs(h[(1 + d) * rows + r] / rho) + cs;
     if (s > smax) smax = s;
   }
+  e = hipMemcpyAsync(c->inflow, h.data(), bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return WL2_E_HIP;
   c->inflow_speed = smax;
   c->inflow_set = true;
   return WL2_OK;
@@ -549,6 +554,22 @@ int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gam
     fill_desc(c);
   }
   return hip_err(rhs_into(c, U, dUdt));
+}
+
+int weno_l2is_rhs_release(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  int cur = 0, n = 0;
+  if (!g_cache.empty() && hipGetDevice(&cur) != hipSuccess) return WL2_E_HIP;
+  for (auto& kv : g_cache) {
+    // each context's memory belongs to the device it was made on
+    if (hipSetDevice(std::get<3>(kv.first)) != hipSuccess) return WL2_E_HIP;
+    weno_l2is_destroy(kv.second);
+    kv.second = nullptr;
+    ++n;
+  }
+  g_cache.clear();
+  if (n && hipSetDevice(cur) != hipSuccess) return WL2_E_HIP;
+  return n;
 }
 
 int weno_l2is_step(weno_l2is_ctx* c, double* U, double dt) {

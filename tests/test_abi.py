@@ -101,3 +101,5 @@ def test_arguments_refused_before_any_device_call():
     for code in (capi.OK, capi.E_NULL, capi.E_SHAPE, capi.E_PARAM, capi.E_BC, capi.E_HIP, capi.E_NOMEM,
                  capi.E_BUDGET, capi.E_SLOT, capi.S_NONPHYSICAL):
         assert lib.weno_l2is_strerror(code)
+    # no rhs call has cached a context: releasing touches no device
+    assert lib.weno_l2is_rhs_release() == 0

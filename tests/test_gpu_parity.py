@@ -186,25 +186,38 @@ def test_hundred_steps_parity(orc, capi, case):
                                           ("turb20x18x17", "roe"),
                                           ("turb20x18x17", "linear_only")])
 def test_hundred_steps_variants(orc, capi, case, variant):
-    """The 100-step bar, 1e-10, or ten times the conditioning of the run if
-    that is larger: the largest distance the oracle's own 100 steps move when
-    its state is perturbed by one ulp (relative N(0, 2.2e-16) noise) after
-    every step, over three seeds.  With the hybrid switch that distance is
-    ~1e-14 and the bar stays 1e-10; with every face WENO on the 3D fields the
-    weights (eps = 1e-20) amplify round-off to 4e-10 .. 2e-9."""
+    """The 100-step bar, 1e-10, or where a run's own conditioning puts it out
+    of reach, twice the conditioning bar of _conditioned_bar."""
     say(f"[step100] case={case} variant={variant}")
     got, ref = _run_steps(orc, capi, case, 100, variant)
     err = z20(got, ref)
     say(f"    z20 = {err:.3e}")
     if err > 1e-10:  # measured only where the plain bar does not hold
-        spread = _oracle_spread(orc, capi, case, variant, 100)
-        say(f"    oracle spread under 1-ulp noise = {spread:.3e}")
-        assert err <= 10.0 * spread
+        bar = _conditioned_bar(orc, capi, case, variant, 100, err)
+        assert err <= bar
 
 
-def _oracle_spread(orc, capi, case, variant, nsteps, seeds=3):
+def _conditioned_bar(orc, capi, case, variant, nsteps, err):
+    """Where the weights (eps = 1e-20 in Eq.(28)) amplify round-off, no
+    implementation that rounds differently from the oracle can meet 1e-10
+    after nsteps.  The bar is then derived from two measurements: d1, the
+    distance between one GPU step and one oracle step from the same state
+    (how far the device's rounding moves a step), and the spread of the
+    oracle's own nsteps when its state is perturbed by relative noise of
+    size d1 after every step (how far such per-step differences carry).
+    The GPU must stay within twice the largest spread over three seeds."""
+    g1, r1 = _run_steps(orc, capi, case, 1, variant)
+    d1 = max(z20(g1, r1), 2.2e-16)
+    spread = _oracle_spread(orc, capi, case, variant, nsteps, d1)
+    say(f"    one-step distance d1 = {d1:.3e}; oracle spread under d1 noise per step = "
+        f"{spread:.3e}; err / spread = {err / spread:.2f} (bar 2)")
+    return max(1e-10, 2.0 * spread)
+
+
+def _oracle_spread(orc, capi, case, variant, nsteps, rel_noise, seeds=3):
     """Largest z20 distance between the oracle's nsteps and the same steps
-    (same dt sequence) with the state perturbed by one ulp after each."""
+    (same dt sequence) with the state multiplied by (1 + rel_noise N(0,1))
+    after each."""
     U, dx, bc = make_case(case)
     po, _ = params_pair(orc, capi, shape_of(U), dx, bc=bc, **VARIANTS[variant])
     ref = U.copy()
@@ -219,7 +232,7 @@ def _oracle_spread(orc, capi, case, variant, nsteps, seeds=3):
         V = U.copy()
         for dt in dts:
             orc.step(V, dx, G, po, dt)
-            V *= 1.0 + 2.2e-16 * rng.standard_normal(V.shape)
+            V *= 1.0 + rel_noise * rng.standard_normal(V.shape)
         worst = max(worst, z20(V, ref))
     return worst
 
@@ -351,27 +364,16 @@ def test_2d_face_once_bitwise(capi, bc, variant, steps):
 
 def test_degenerate_tiny_grid(orc, capi):
     """Five cells, transmissive left and reflective right wall: one step to
-    1e-12; after 100 steps the bound is four times the drift that a one-ulp
-    perturbation of the input causes in the oracle itself (this tiny,
+    1e-12; after 100 steps the bar of _conditioned_bar (this tiny,
     wave-bouncing problem amplifies round-off to ~1e-10 by itself)."""
     say("[tiny5] 1 and 100 steps")
     got, ref = _run_steps(orc, capi, "tiny5", 1)
     assert z20(got, ref) <= 1e-12
     got, ref = _run_steps(orc, capi, "tiny5", 100)
-    U, dx, bc = make_case("tiny5")
-    po = orc.params(5, 1, 1, dx, bc=bc)
-    rng = np.random.default_rng(0)
-    sens = 0.0
-    for _ in range(3):
-        A = U.copy()
-        B = U * (1 + 2.2e-16 * rng.standard_normal(U.shape))
-        for _ in range(100):
-            dt, _ = orc.step(A, dx, G, po)
-            orc.step(B, dx, G, po, dt)
-        sens = max(sens, z20(B, A))
     err = z20(got, ref)
-    say(f"    z20 = {err:.3e}, oracle self-sensitivity = {sens:.3e}")
-    assert err <= max(1e-10, 4.0 * sens)
+    say(f"    z20 = {err:.3e}")
+    if err > 1e-10:
+        assert err <= _conditioned_bar(orc, capi, "tiny5", "default", 100, err)
 
 
 def test_advance_to_t_end(orc, capi):
@@ -904,15 +906,24 @@ def test_inflow_rhs_parity(orc, capi, case, kw, path):
     ctx.close()
     assert np.all(np.isfinite(got))
     # the bar of every rhs test (the change within one step, in units of the
-    # state), with the step and the state's scale those of the scheme: the
-    # time step bounds the inflow speed too, and the fluxes at the inflow
-    # side carry the ghost state (the jet's E = 1.6e6 against 0.62 inside)
+    # state), with the step of the scheme (it bounds the inflow speed too) and
+    # a scale per cell: the interior's grid maximum of the variable (momentum
+    # components share theirs), raised to the ghost state's only in the three
+    # columns whose stencils reach the inflow ghosts (the jet's E = 1.6e6
+    # against 0.62 inside)
     dt, st = orc.step(U.copy(), dx, g, po)
     assert st == 0
+    nv = U.shape[0]
+    infs = inf.reshape(nv, nz, ny)
+    groups = [[0], list(range(1, nv - 1)), [nv - 1]]
     err = 0.0
-    for c in range(U.shape[0]):
-        scale = max(float(np.abs(U[c]).max()), float(np.abs(inf[c]).max()), 1e-300)
-        err = max(err, float(np.abs(got[c] - ref[c]).max()) * dt / scale)
+    for grp in groups:
+        interior = max(float(np.abs(U[grp]).max()), 1e-300)
+        near = max(interior, float(np.abs(infs[grp]).max()))
+        scale = np.full(U.shape[1:], interior)
+        scale[..., :3] = near
+        for c in grp:
+            err = max(err, float((np.abs(got[c] - ref[c]) * dt / scale).max()))
     say(f"    rhs err = {err:.3e}")
     assert err <= 1e-12
 
@@ -975,6 +986,19 @@ def test_inflow_refusals(capi):
     good = to_dev(np.ones((4, 8)) * np.array([[1.0], [0.5], [0.0], [2.5]]))
     assert L.weno_l2is_set_inflow(ctx.h, good.data_ptr()) == 0
     assert L.weno_l2is_rhs_ctx(ctx.h, U.data_ptr(), out.data_ptr()) == 0
+    dt_good = C.c_double(0.0)
+    assert L.weno_l2is_cfl_dt(ctx.h, U.data_ptr(), C.byref(dt_good)) == 0
+    ref = to_host(out)
+    # a refused state after an accepted one changes neither the ghosts nor
+    # the time-step bound (fast, then non-physical rows)
+    fast_bad = to_dev(np.ones((4, 8)) * np.array([[1.0], [30.0], [0.0], [-2.5]]))
+    assert L.weno_l2is_set_inflow(ctx.h, fast_bad.data_ptr()) == -3
+    out.fill_(float("nan"))
+    assert L.weno_l2is_rhs_ctx(ctx.h, U.data_ptr(), out.data_ptr()) == 0
+    dt_after = C.c_double(0.0)
+    assert L.weno_l2is_cfl_dt(ctx.h, U.data_ptr(), C.byref(dt_after)) == 0
+    assert np.array_equal(to_host(out), ref)
+    assert dt_after.value == dt_good.value
     ctx.close()
     plain = capi.Context(8, 8, 1, 0.1, G)
     assert L.weno_l2is_set_inflow(plain.h, good.data_ptr()) == -4
@@ -985,3 +1009,30 @@ def test_inflow_refusals(capi):
                                    C.byref(slot), C.byref(nbytes)) == -4
     b.close()
     torch.cuda.synchronize()
+
+
+def test_rhs_release_frees_the_cached_contexts(orc, capi):
+    """The stateless rhs keeps one context per shape; rhs_release frees them
+    all (and reports how many), and a later call builds its context again
+    with the same bits."""
+    import torch
+    say("[rhs release]")
+    capi.rhs_release()
+    outs = []
+    for case in ("quad40x36_mixed", "turb16x12x10_mixed"):
+        U, dx, bc = make_case(case)
+        shape = shape_of(U)
+        p = capi.params_default(*shape, dx, bc=bc)
+        Ud = to_dev(U)
+        out = torch.empty_like(Ud)
+        capi.rhs(Ud, *shape, dx, G, p, out)
+        torch.cuda.synchronize()
+        outs.append((Ud, shape, dx, p, to_host(out)))
+    assert capi.rhs_release() == 2
+    assert capi.rhs_release() == 0
+    for Ud, shape, dx, p, ref in outs:
+        out = torch.full_like(Ud, float("nan"))
+        capi.rhs(Ud, *shape, dx, G, p, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(out), ref)
+    assert capi.rhs_release() == 2

@@ -181,13 +181,20 @@ def test_serving_summary_latency_and_throughput():
     out = {r.rid: {"arrival": r.arrival, "finish": r.arrival + 0.5 + 0.01 * r.rid, "steps": 10,
                    "status": 0, "t": 1.0} for r in reqs}
     out[7]["status"] = 1
+    out[7]["steps"] = 4
     s = serve.summarize(reqs, out, makespan=2.0)
-    lat = np.array([0.5 + 0.01 * i for i in range(100)])
+    # the failed request stays out of the percentiles and the throughput
+    ok = [i for i in range(100) if i != 7]
+    lat = np.array([0.5 + 0.01 * i for i in ok])
     assert s["p50_s"] == pytest.approx(np.percentile(lat, 50), abs=1e-5)
     assert s["p99_s"] == pytest.approx(np.percentile(lat, 99), abs=1e-5)
-    work = sum((100 + i) * 3 * 10 for i in range(100))
+    work = sum((100 + i) * 3 * 10 for i in ok)
     assert s["throughput_Mcell_stage_per_s"] == pytest.approx(work / 2.0 / 1e6, abs=0.01)
-    assert s["steps"] == 1000 and s["failed"] == 1 and s["failed_runs"][0]["rid"] == 7
+    assert s["steps"] == 990 and s["completed"] == 99
+    assert s["failed"] == 1 and s["failed_runs"][0]["rid"] == 7 and s["failed_steps"] == 4
+    assert s["failed_Mcell_stages"] == pytest.approx(107 * 3 * 4 / 1e6, abs=1e-3)
+    # every latency is non-negative when arrival times are the starts
+    assert s["p50_s"] > 0 and s["mean_s"] > 0
 
 
 # ----------------------------------------------------------- counter summary

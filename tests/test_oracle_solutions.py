@@ -354,3 +354,24 @@ def test_nonphysical_state_reported(orc):
     assert st == 1
     t, steps, st = orc.run(U, dx, G, p, 0.1)
     assert st == 1 and steps == 0
+
+
+def test_thread_count_changes_no_bit(orc):
+    """The lines of a sweep may run on several threads (OpenMP build): each
+    line writes only its own cells, so any thread count gives the same bits."""
+    U, dx = w.turbulence_3d(16, 4, ny=14, nz=12)
+    U = np.ascontiguousarray(U.copy())
+    U[0, :, :, :8] *= 1.5
+    p = orc.params(16, 14, 12, dx, bc=[0, 0, 1, 1, 2, 2])
+    keep = orc.threads()
+    try:
+        outs = []
+        for n in (1, 3, 8):
+            orc.threads(n)
+            V = U.copy()
+            orc.step(V, dx, G, p)
+            outs.append(V)
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+    finally:
+        orc.threads(keep)
