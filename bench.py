@@ -222,6 +222,47 @@ def other_configs(torch, capi, workloads):
     return out
 
 
+def weighting_ratios(torch, capi, workloads, steps=200):
+    """Relative cost of the schemes the paper compares (Sec. 4.5-4.6, Tables
+    1-2 time the whole runs on a CPU), here as GPU time per step of the 2D
+    four-quadrant 1024^2 problem with the paper's 2D splitting (global
+    Lax-Friedrichs): the present hybrid scheme (regularized weights, Eq.(28),
+    with the switch of Eq.(33)-(35)), the WENO-IS scheme of Wang et al.
+    (pure WENO with the weights of Eq.(14)-(15)), the original WENO-IS
+    weights (Eq.(8)), pure regularized WENO (switch off) and the optimal
+    linear scheme alone (every face on the linear branch)."""
+    U0, dx, _ = workloads.four_quadrant_2d(1024, 1024, 2024)
+    shape = (1024, 1024, 1)
+    schemes = {"present": {}, "weno_is_b01": {"hybrid": 2, "weights": 2},
+               "weno_is": {"hybrid": 2, "weights": 1}, "weno_l2is_no_switch": {"hybrid": 2},
+               "linear_only": {"hybrid": 3}}
+    out = {}
+    for name, kw in schemes.items():
+        ctx = capi.Context(*shape, dx, GAMMA, capi.params_default(*shape, dx, split=1, **kw))
+        ms = None
+        for rep in range(2):  # warm-up run, then the timed one
+            Ud = torch.from_numpy(U0).cuda()
+            ctx.set_time(0.0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            ctx.advance(Ud, steps, 1e300)
+            e1.record(ctx.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+        out[name] = {"ms_per_step": round(ms / steps, 5), "status": ctx.status()}
+        ctx.close()
+        del Ud
+    base = out["present"]["ms_per_step"]
+    out["present_over"] = {k: round(base / v["ms_per_step"], 3) for k, v in out.items()
+                           if k != "present"}
+    out["config"] = f"2D four-quadrant 1024^2, {steps} steps, global LF splitting, seed 2024"
+    out["paper_context"] = ("CPU wall time ratios, unnamed hardware: Present / WENO-Z = 0.728 (DMR "
+                            "512x128) and 0.772 (viscous shock tube); Present / WENO-JS = 0.840, "
+                            "0.795; Present / WENO-HY = 1.262, 1.142")
+    log(f"[bench]   weighting ratios: {out['present_over']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +279,8 @@ def main():
                     help="skip the 1D / 2D single-grid workloads")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the 3D WENO-only / linear-only timings")
+    ap.add_argument("--no-ratios", action="store_true",
+                    help="skip the relative cost of the compared weightings (2D 1024^2)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the batched-serving leg (Poisson stream of 1D/2D Riemann runs)")
     ap.add_argument("--serve-requests", type=int, default=1024)
@@ -245,6 +288,8 @@ def main():
                     help="requests in the plain per-grid baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of a state array (known bytes) for counter scaling")
+    ap.add_argument("--start-step", type=int, default=0,
+                    help="advance the field this many steps before the warm-up (developed regime)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); the hot path "
@@ -269,6 +314,10 @@ def main():
     # clock target is never reached); from the second step of a call the
     # CFL maximum comes folded out of the previous step's last stage
     T_END = 1e300
+    if args.start_step:
+        log(f"[bench] advancing {args.start_step} steps to the developed field")
+        ctx.advance(Ud, args.start_step, T_END)
+        torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps")
     ctx.advance(Ud, args.warmup, T_END)
     torch.cuda.synchronize()
@@ -361,6 +410,11 @@ def main():
         log("[bench] 1D / 2D configurations")
         others = other_configs(torch, capi, workloads)
 
+    ratios = None
+    if not args.no_ratios and not args.no_configs:
+        log("[bench] relative cost of the compared weightings (2D 1024^2)")
+        ratios = weighting_ratios(torch, capi, workloads)
+
     serving = None
     if not args.no_serve:
         # batched serving: 1024 independent 1D/2D Riemann runs arriving as a
@@ -405,6 +459,7 @@ def main():
             "cells": ncell, "rk_stages_per_step": 3, "seed": SEED,
             "hybrid": {0: "per-field", 1: "per-face", 2: "weno-only", 3: "linear-only"}[args.hybrid],
             "kernel_path": {0: "fused stage kernel", 1: "per-direction sweeps"}[args.path],
+            "start_step": args.start_step,
             "weno_face_fraction_xyz": [round(f, 6) for f in weno_frac],
             "weno_face_field_fraction_xyz": [round(f, 6) for f in weno_field_frac],
         },
@@ -417,6 +472,7 @@ def main():
         },
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kt.items()},
         "configs_1d_2d": others,
+        "weighting_ratios": ratios,
         "serving": serving,
         "cpu_baseline": cpu,
     }

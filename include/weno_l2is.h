@@ -75,6 +75,14 @@ enum { WL2_SPLIT_LLF = 0, WL2_SPLIT_LF = 1, WL2_SPLIT_ROE = 2 };
 enum { WL2_HYB_PER_FIELD = 0, WL2_HYB_PER_FACE = 1, WL2_HYB_WENO_ONLY = 2,
        WL2_HYB_LINEAR_ONLY = 3 };
 
+/* Weights of the nonlinear reconstruction: L2IS = the regularized weights of
+ * the present scheme, Eq.(28) (default); IS = the original WENO-IS weights,
+ * Eq.(8); IS_B01 = WENO-IS with the 3-point indicator beta_01 of Eq.(15)
+ * multiplying the ratios of the two 2-point stencils, Eq.(14) (the
+ * "WENO-IS" scheme the paper compares against).  The two comparison forms
+ * do not use lambda; with WL2_HYB_WENO_ONLY they are those schemes. */
+enum { WL2_W_L2IS = 0, WL2_W_IS = 1, WL2_W_IS_B01 = 2 };
+
 typedef struct weno_l2is_params {
   double cfl;       /* CFL number, 0.5 (Sec. 4)                               */
   double c_reg;     /* c in lambda = c * sigma^s, Eq.(32): 1                  */
@@ -85,6 +93,7 @@ typedef struct weno_l2is_params {
   int hybrid;       /* WL2_HYB_*                                              */
   int bc[6];        /* x-, x+, y-, y+, z-, z+ : WL2_BC_*; periodic is paired  */
   double thr_L[3];  /* L of Eq.(35) per direction; default n_d * dx           */
+  int weights;      /* WL2_W_*: weights of the WENO branch; default L2IS      */
 } weno_l2is_params;
 
 typedef struct weno_l2is_ctx weno_l2is_ctx;

@@ -120,8 +120,8 @@ int orc_face_flux(int nvar, int dir, double gamma, const orc_params *p,
         ap[m] = fp[m];          /* f+_{j-2} .. f+_{j+2} */
         am[m] = fm[5 - m];      /* f-_{j+3} .. f-_{j-1} (mirrored) */
       }
-      fs[s] = orc_weno_l2is(ap, lr, p->eps_w, 0) +
-              orc_weno_l2is(am, lr, p->eps_w, 0);         /* Eq.(22)-(23) */
+      fs[s] = orc_weno(ap, p->weights, lr, p->eps_w, 0) +
+              orc_weno(am, p->weights, lr, p->eps_w, 0);  /* Eq.(22)-(23) */
     }
   }
 

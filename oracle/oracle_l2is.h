@@ -33,6 +33,13 @@ enum {
   ORC_HYB_LINEAR_ONLY = 3 /* always linear (optimal upwind scheme)          */
 };
 
+enum {
+  ORC_W_L2IS = 0,   /* regularized weights of the present scheme, Eq.(28)    */
+  ORC_W_IS = 1,     /* original WENO-IS weights, Eq.(8)                       */
+  ORC_W_IS_B01 = 2  /* WENO-IS with beta_01 on the 2-point stencils,
+                       Eq.(14)-(15) (the "WENO-IS" of the comparisons)       */
+};
+
 typedef struct {
   double cfl;       /* CFL number (Sec. 4: 0.5)                                */
   double c_reg;     /* c in lambda = c * sigma, Eq.(32): 1                     */
@@ -46,10 +53,11 @@ typedef struct {
   const double *inflow; /* ORC_BC_INFLOW on bc[0]: the conserved state of the
                            ghosts left of x line y, inflow[v*ny + y]; else
                            unused (Sec. 4.7, the jet's left boundary)      */
+  int weights;      /* ORC_W_*: weights of the nonlinear reconstruction       */
 } orc_params;
 
 /* Fill defaults for a grid: thr_L[d] = n_d * dx, transmissive boundaries,
- * inflow = NULL. */
+ * inflow = NULL, weights ORC_W_L2IS. */
 int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx);
 
 /* Scalar WENO-L2IS reconstruction at x_{j+1/2} from a[0..4] = f_{j-2..j+2}
@@ -57,6 +65,10 @@ int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx);
  * dbg (may be NULL) receives 17 values:
  *   q0..q3, beta0..beta3, tau5, E0..E3, omega0..omega3. */
 double orc_weno_l2is(const double a[5], double lam, double eps_w, double *dbg);
+
+/* The same reconstruction with the weights `weights` (ORC_W_*); lam is read
+ * by ORC_W_L2IS only.  dbg as above (E_k is computed in every case). */
+double orc_weno(const double a[5], int weights, double lam, double eps_w, double *dbg);
 
 /* Roe average between UL and UR and the eigensystem of the Roe Jacobian along
  * direction dir (0,1,2).  L and R are nvar x nvar row-major, L = R^{-1};

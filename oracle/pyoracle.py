@@ -26,6 +26,7 @@ SOURCES = ["weno_scalar.c", "charsys.c", "face.c", "solver.c"]
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
+W_L2IS, W_IS, W_IS_B01 = 0, 1, 2
 
 
 def build(verbose: bool = False, src_dir: str = HERE, out: str = DEFAULT_LIB) -> str:
@@ -53,6 +54,7 @@ class Params(C.Structure):
         ("bc", C.c_int * 6),
         ("thr_L", C.c_double * 3),
         ("inflow", C.POINTER(C.c_double)),
+        ("weights", C.c_int),
     ]
 
 
@@ -71,6 +73,8 @@ def lib():
         L.orc_params_default.argtypes = [pp, C.c_int, C.c_int, C.c_int, C.c_double]
         L.orc_weno_l2is.argtypes = [dp, C.c_double, C.c_double, dp]
         L.orc_weno_l2is.restype = C.c_double
+        L.orc_weno.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_weno.restype = C.c_double
         L.orc_roe_eigen.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, dp, dp, dp, dp]
         L.orc_phys_flux.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, dp]
         L.orc_face_flux.argtypes = [C.c_int, C.c_int, C.c_double, pp, C.c_double,
@@ -138,6 +142,15 @@ def weno_l2is(a, lam: float, eps_w: float = 1e-20):
     a = np.ascontiguousarray(a, dtype=np.float64)
     dbg = np.zeros(17)
     f = lib().orc_weno_l2is(_dp(a), float(lam), float(eps_w), _dp(dbg))
+    return f, {"q": dbg[0:4].copy(), "beta": dbg[4:8].copy(), "tau5": dbg[8],
+               "E": dbg[9:13].copy(), "omega": dbg[13:17].copy()}
+
+
+def weno(a, weights: int, lam: float = 0.0, eps_w: float = 1e-20):
+    """Scalar reconstruction with the weights W_*; returns (fhat, dict)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    dbg = np.zeros(17)
+    f = lib().orc_weno(_dp(a), int(weights), float(lam), float(eps_w), _dp(dbg))
     return f, {"q": dbg[0:4].copy(), "beta": dbg[4:8].copy(), "tau5": dbg[8],
                "E": dbg[9:13].copy(), "omega": dbg[13:17].copy()}
 

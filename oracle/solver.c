@@ -49,6 +49,7 @@ static int check_params(const grid_t *g, const orc_params *p) {
     if (!(p->thr_L[d] > 0.0)) return -1;
   }
   if (p->split < 0 || p->split > 2 || p->hybrid < 0 || p->hybrid > 3) return -1;
+  if (p->weights < ORC_W_L2IS || p->weights > ORC_W_IS_B01) return -1;
   return 0;
 }
 
@@ -63,6 +64,7 @@ int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx) {
   p->hybrid = ORC_HYB_PER_FIELD;
   for (d = 0; d < 6; ++d) p->bc[d] = ORC_BC_TRANSMISSIVE;
   p->inflow = 0;
+  p->weights = ORC_W_L2IS;
   p->thr_L[0] = nx * dx;
   p->thr_L[1] = ny * dx;
   p->thr_L[2] = nz * dx;

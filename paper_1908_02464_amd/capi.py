@@ -39,6 +39,7 @@ class Params(C.Structure):
         ("hybrid", C.c_int),
         ("bc", C.c_int * 6),
         ("thr_L", C.c_double * 3),
+        ("weights", C.c_int),
     ]
 
 

@@ -399,6 +399,7 @@ int weno_l2is_params_default(weno_l2is_params* p, int nx, int ny, int nz, double
   p->thr_L[0] = nx * dx;
   p->thr_L[1] = ny * dx;
   p->thr_L[2] = nz * dx;
+  p->weights = WL2_W_L2IS;
   return WL2_OK;
 }
 

@@ -35,6 +35,7 @@ inline void fill_grid_desc(const int n[3], int dim, double dx, double gamma,
   }
   ph.split = p.split;
   ph.hybrid = p.hybrid;
+  ph.weights = p.weights;
 }
 
 // Argument checks shared by every entry point that takes a grid.
@@ -50,6 +51,7 @@ inline int validate_grid(int nx, int ny, int nz, double dx, double gamma,
       p->thr_alpha < 0 || p->thr_alpha > 64)
     return WL2_E_PARAM;
   if (p->split < 0 || p->split > 2 || p->hybrid < 0 || p->hybrid > 3) return WL2_E_PARAM;
+  if (p->weights < WL2_W_L2IS || p->weights > WL2_W_IS_B01) return WL2_E_PARAM;
   const int dim = grid_dim(ny, nz);
   const int n[3] = {nx, ny, nz};
   for (int d = 0; d < dim; ++d) {

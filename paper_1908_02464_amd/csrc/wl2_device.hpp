@@ -30,6 +30,9 @@ namespace wl2 {
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
 enum { SPLIT_LLF = 0, SPLIT_LF = 1, SPLIT_ROE = 2 };
 enum { HYB_PER_FIELD = 0, HYB_PER_FACE = 1, HYB_WENO_ONLY = 2, HYB_LINEAR_ONLY = 3 };
+// weights of the WENO branch: regularized Eq.(28), original WENO-IS Eq.(8),
+// WENO-IS with beta_01 on the 2-point stencils Eq.(14)-(15)
+enum { W_L2IS = 0, W_IS = 1, W_IS_B01 = 2 };
 // What a stage kernel does with the face-flux difference dU of Eq.(19):
 // write it, add it to the output, or fuse it into the SSP-RK3 combination.
 enum { OUT_WRITE = 0, OUT_ACCUM = 1, OUT_RK = 2 };
@@ -51,6 +54,7 @@ struct KPhys {
   double c_reg, eps_w;
   double eps_thr[3];   // switch threshold C (dx/L_d)^alpha per direction
   int split, hybrid;
+  int weights;         // W_*: weights of the WENO branch
 };
 
 // One slot of the running CFL maximum (max of sum_d(|u_d|+c) as raw bits;
@@ -432,9 +436,10 @@ __device__ __forceinline__ unsigned face_detector(const CellRec<NV>& c0, const C
 
 // ---------------------------------------------------------------- WENO-L2IS
 // Scalar reconstruction at x_{j+1/2} from f_{j-2..j+2} (Eq.(5),(6),(11),
-// (27),(28)), optimal weights d = (0.4, 0.2, 0.3, 0.1).
+// (27),(28)), optimal weights d = (0.4, 0.2, 0.3, 0.1); wts selects the
+// comparison weights of Eq.(8) or Eq.(14)-(15) instead (lam unused there).
 __device__ __forceinline__ double weno_l2is(double fm2, double fm1, double f0, double fp1,
-                                            double fp2, double lam, double eps_w) {
+                                            double fp2, double lam, double eps_w, int wts) {
   const double q0 = 0.5 * (f0 + fp1);
   const double q1 = 0.5 * (3.0 * f0 - fm1);
   const double q2 = (2.0 * f0 + 5.0 * fp1 - fp2) * (1.0 / 6.0);
@@ -449,12 +454,27 @@ __device__ __forceinline__ double weno_l2is(double fm2, double fm1, double f0, d
   const double t2 = (fp2 - fm2) - 2.0 * (fp1 - fm1);
   const double tau5 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
   const double e = fm1 - 2.0 * f0 + fp1;
-  const double E01 = e * e * (1.0 / 45.0);
-  const double lt = lam * tau5;
-  const double a0 = 0.4 * (1.0 + lt / (lam * b0 + E01 + eps_w));
-  const double a1 = 0.2 * (1.0 + lt / (lam * b1 + E01 + eps_w));
-  const double a2 = 0.3 * (1.0 + lt / (lam * b2 + eps_w));
-  const double a3 = 0.1 * (1.0 + lt / (lam * b3 + eps_w));
+  double a0, a1, a2, a3;
+  if (wts == W_L2IS) {
+    const double E01 = e * e * (1.0 / 45.0);
+    const double lt = lam * tau5;
+    a0 = 0.4 * (1.0 + lt / (lam * b0 + E01 + eps_w));
+    a1 = 0.2 * (1.0 + lt / (lam * b1 + E01 + eps_w));
+    a2 = 0.3 * (1.0 + lt / (lam * b2 + eps_w));
+    a3 = 0.1 * (1.0 + lt / (lam * b3 + eps_w));
+  } else {
+    double r0 = tau5 / (b0 + eps_w), r1 = tau5 / (b1 + eps_w);
+    if (wts == W_IS_B01) {
+      const double g = fm1 - fp1;
+      const double r01 = tau5 / ((13.0 / 12.0) * e * e + 0.25 * g * g + eps_w);
+      r0 *= r01;
+      r1 *= r01;
+    }
+    a0 = 0.4 * (1.0 + r0);
+    a1 = 0.2 * (1.0 + r1);
+    a2 = 0.3 * (1.0 + tau5 / (b2 + eps_w));
+    a3 = 0.1 * (1.0 + tau5 / (b3 + eps_w));
+  }
   return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) / ((a0 + a1) + (a2 + a3));
 }
 
@@ -517,8 +537,8 @@ __device__ __forceinline__ double weno_field(const CellRec<NV>& c0, const CellRe
   (void)p5;
   (void)m0;
   // f+ on (f+_{j-2..j+2}); f- on the mirrored (f-_{j+3..j-1})  (Eq.(22)-(23))
-  const double fw = weno_l2is(p0, p1, p2, p3, p4, lam, ph.eps_w) +
-                    weno_l2is(m5, m4, m3, m2, m1, lam, ph.eps_w);
+  const double fw = weno_l2is(p0, p1, p2, p3, p4, lam, ph.eps_w, ph.weights) +
+                    weno_l2is(m5, m4, m3, m2, m1, lam, ph.eps_w, ph.weights);
   return fw - (LFk + al * dvk);
 }
 

@@ -249,9 +249,10 @@ struct WinSrc {  // the owner's z window (registers)
 // (11), (27), (28); optimal weights d = (0.4, 0.2, 0.3, 0.1)), the quotients
 // through fast_rcp: the same formula as weno_l2is, a few ulp apart, with
 // shorter dependency chains than correctly rounded division.  Every
-// denominator is at least eps_w > 0 (the weight sum at least 1).
+// denominator is at least eps_w > 0 (the weight sum at least 1).  wts
+// selects the comparison weights of Eq.(8) or Eq.(14)-(15) (lam unused).
 __device__ __forceinline__ double weno_l2is_lr(double fm2, double fm1, double f0, double fp1,
-                                               double fp2, double lam, double eps_w) {
+                                               double fp2, double lam, double eps_w, int wts) {
   const double q0 = 0.5 * (f0 + fp1);
   const double q1 = 0.5 * (3.0 * f0 - fm1);
   const double q2 = (2.0 * f0 + 5.0 * fp1 - fp2) * (1.0 / 6.0);
@@ -266,12 +267,27 @@ __device__ __forceinline__ double weno_l2is_lr(double fm2, double fm1, double f0
   const double t2 = (fp2 - fm2) - 2.0 * (fp1 - fm1);
   const double tau5 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
   const double e = fm1 - 2.0 * f0 + fp1;
-  const double E01 = e * e * (1.0 / 45.0);
-  const double lt = lam * tau5;
-  const double a0 = 0.4 * (1.0 + lt * fast_rcp(lam * b0 + E01 + eps_w));
-  const double a1 = 0.2 * (1.0 + lt * fast_rcp(lam * b1 + E01 + eps_w));
-  const double a2 = 0.3 * (1.0 + lt * fast_rcp(lam * b2 + eps_w));
-  const double a3 = 0.1 * (1.0 + lt * fast_rcp(lam * b3 + eps_w));
+  double a0, a1, a2, a3;
+  if (wts == W_L2IS) {
+    const double E01 = e * e * (1.0 / 45.0);
+    const double lt = lam * tau5;
+    a0 = 0.4 * (1.0 + lt * fast_rcp(lam * b0 + E01 + eps_w));
+    a1 = 0.2 * (1.0 + lt * fast_rcp(lam * b1 + E01 + eps_w));
+    a2 = 0.3 * (1.0 + lt * fast_rcp(lam * b2 + eps_w));
+    a3 = 0.1 * (1.0 + lt * fast_rcp(lam * b3 + eps_w));
+  } else {
+    double r0 = tau5 * fast_rcp(b0 + eps_w), r1 = tau5 * fast_rcp(b1 + eps_w);
+    if (wts == W_IS_B01) {
+      const double g = fm1 - fp1;
+      const double r01 = tau5 * fast_rcp((13.0 / 12.0) * e * e + 0.25 * g * g + eps_w);
+      r0 *= r01;
+      r1 *= r01;
+    }
+    a0 = 0.4 * (1.0 + r0);
+    a1 = 0.2 * (1.0 + r1);
+    a2 = 0.3 * (1.0 + tau5 * fast_rcp(b2 + eps_w));
+    a3 = 0.1 * (1.0 + tau5 * fast_rcp(b3 + eps_w));
+  }
   return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * fast_rcp((a0 + a1) + (a2 + a3));
 }
 
@@ -299,8 +315,8 @@ __device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, d
   }
   const double t = dvk * s.irho;
   const double lam = ph.c_reg * (t * t);  // Eq.(32)
-  const double fw = weno_l2is_lr(fp[0], fp[1], fp[2], fp[3], fp[4], lam, ph.eps_w) +
-                    weno_l2is_lr(fm[5], fm[4], fm[3], fm[2], fm[1], lam, ph.eps_w);
+  const double fw = weno_l2is_lr(fp[0], fp[1], fp[2], fp[3], fp[4], lam, ph.eps_w, ph.weights) +
+                    weno_l2is_lr(fm[5], fm[4], fm[3], fm[2], fm[1], lam, ph.eps_w, ph.weights);
   return fw - (LFk + al * dvk);
 }
 

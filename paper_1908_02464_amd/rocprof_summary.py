@@ -67,9 +67,23 @@ def _rows(d, pattern):
         return list(csv.DictReader(fh))
 
 
-def trace_stats(d, kernel):
-    rows = _rows(d, "*kernel_stats.csv")
+def trace_stats(d, kernel, last=0):
+    """Per kernel name: calls and durations from the stats file, or with
+    last > 0 from the last `last` dispatches of the trace file."""
     out = {}
+    if last:
+        rows = _rows(d, "*kernel_trace.csv")
+        by = {}
+        for r in rows:
+            if kernel in r["Kernel_Name"]:
+                by.setdefault(r["Kernel_Name"], []).append(
+                    (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        for name, v in by.items():
+            dur = [x[1] for x in sorted(v)[-last:]]
+            out[name] = {"calls": len(dur), "avg_ns": statistics.mean(dur), "min_ns": min(dur),
+                         "max_ns": max(dur), "of_calls": len(v)}
+        return out
+    rows = _rows(d, "*kernel_stats.csv")
     for r in rows:
         if kernel in r["Name"]:
             out[r["Name"]] = {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
@@ -78,10 +92,15 @@ def trace_stats(d, kernel):
     return out
 
 
+LAST = 0  # > 0: counters of the kernel's last LAST dispatches only
+
+
 def counter(d, kernel, name):
     rows = _rows(d, "*counter_collection.csv")
-    vals = [float(r["Counter_Value"]) for r in rows
-            if kernel in r["Kernel_Name"] and r["Counter_Name"] == name]
+    sel = [r for r in rows if kernel in r["Kernel_Name"] and r["Counter_Name"] == name]
+    if LAST:
+        sel = sorted(sel, key=lambda r: int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0))[-LAST:]
+    vals = [float(r["Counter_Value"]) for r in sel]
     cal = [float(r["Counter_Value"]) for r in rows
            if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == name
            and int(r["Grid_Size"]) > 1000]
@@ -96,11 +115,19 @@ def main():
     ap.add_argument("--write")
     ap.add_argument("--valu")
     ap.add_argument("--command", required=True)
+    ap.add_argument("--pmc", nargs="*", default=[],
+                    help="further counter runs: every counter found for the kernel, per dispatch")
+    ap.add_argument("--last", type=int, default=0,
+                    help="use only the kernel's last N dispatches (trace and counters)")
     ap.add_argument("--workload", default="3D Euler turbulence 256^3 periodic, FP64")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
+    global LAST
+    LAST = a.last
     info = {"kernel": a.kernel, "workload": a.workload, "command": a.command,
-            "source_hash": source_hash(), "trace": trace_stats(a.trace, a.kernel)}
+            "source_hash": source_hash(), "trace": trace_stats(a.trace, a.kernel, a.last)}
+    if a.last:
+        info["dispatches_used"] = f"last {a.last} of the kernel"
     if a.fetch and a.write:
         fv, fc = counter(a.fetch, a.kernel, "FETCH_SIZE")
         wv, wc = counter(a.write, a.kernel, "WRITE_SIZE")
@@ -130,6 +157,15 @@ def main():
         if all(k in v for k in need):
             info["fp64_flops_per_launch"] = 64.0 * (2.0 * v[need[2]] + v[need[0]] + v[need[1]] +
                                                     v[need[3]])
+    if a.pmc:
+        extra = {}
+        for d in a.pmc:
+            names = sorted({r["Counter_Name"] for r in _rows(d, "*counter_collection.csv")})
+            for name in names:
+                vals, _ = counter(d, a.kernel, name)
+                if vals:
+                    extra[name + "_per_dispatch"] = statistics.mean(vals)
+        info["pmc"] = extra
     lines = ["# rocprofv3 summary: " + a.kernel, "",
              "command: " + a.command, "",
              "```json", json.dumps(info, indent=1), "```", ""]

@@ -339,7 +339,8 @@ def test_fused_zchunk_bitwise_and_autotuner(capi):
 def test_batch_scheme_variants_and_boundaries(orc, capi):
     """One batch holding runs with different schemes and boundaries (Roe
     splitting, per-face switch, WENO only, linear only on smooth data, where
-    it stays physical; periodic and reflective walls): each run equals, bit for bit, its single-grid run
+    it stays physical, the comparison weights of Eq.(8) and Eq.(14)-(15);
+    periodic and reflective walls): each run equals, bit for bit, its single-grid run
     with the same parameters, and the oracle advanced to the same end time
     within 1e-10."""
     import torch
@@ -354,7 +355,9 @@ def test_batch_scheme_variants_and_boundaries(orc, capi):
             ("two_state_reflective_face", U3, dx3, 0.05, dict(bc=[2, 2, 1, 1, 1, 1], hybrid=1)),
             ("adv_periodic_linear", U2, dx2, 0.2, dict(bc=[0, 0, 1, 1, 1, 1], hybrid=3)),
             ("quad_face_mixed_bc", U4, dx4, 0.03, dict(bc=[0, 0, 2, 2, 1, 1], hybrid=1)),
-            ("quad_roe_reflective", U5, dx5, 0.04, dict(bc=[2, 1, 1, 2, 1, 1], split=capi.SPLIT_ROE))]
+            ("quad_roe_reflective", U5, dx5, 0.04, dict(bc=[2, 1, 1, 2, 1, 1], split=capi.SPLIT_ROE)),
+            ("sod_weno_is_b01", U1, dx1, 0.08, dict(hybrid=2, weights=2)),
+            ("quad_hybrid_is", U4, dx4, 0.03, dict(weights=1))]
     eng = capi.Batch(128 * MiB, 16)
     slots = {}
     for name, U, dx, te, kw in runs:

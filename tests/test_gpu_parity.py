@@ -77,6 +77,12 @@ VARIANTS = {
     "linear_only": {"hybrid": 3},
     "lf": {"split": 1},
     "roe": {"split": 2},
+    # the comparison weightings: original WENO-IS (Eq.(8)) and WENO-IS with
+    # beta_01 (Eq.(14)-(15)) as pure WENO schemes, and beta_01 weights under
+    # the hybrid switch
+    "weno_is": {"hybrid": 2, "weights": 1},
+    "weno_is_b01": {"hybrid": 2, "weights": 2},
+    "hybrid_b01": {"weights": 2},
 }
 
 
@@ -184,7 +190,10 @@ def test_hundred_steps_parity(orc, capi, case):
                                           ("quad40x36_mixed", "per_face"),
                                           ("turb16x12x10_mixed", "weno_only"),
                                           ("turb20x18x17", "roe"),
-                                          ("turb20x18x17", "linear_only")])
+                                          ("turb20x18x17", "linear_only"),
+                                          ("sod200", "weno_is_b01"), ("quad67x45", "weno_is"),
+                                          ("turb16x12x10_mixed", "weno_is_b01"),
+                                          ("shu1600", "hybrid_b01"), ("turb20x18x17", "weno_is")])
 def test_hundred_steps_variants(orc, capi, case, variant):
     """The 100-step bar, 1e-10, or where a run's own conditioning puts it out
     of reach, twice the conditioning bar of _conditioned_bar."""
@@ -1036,3 +1045,86 @@ def test_rhs_release_frees_the_cached_contexts(orc, capi):
         torch.cuda.synchronize()
         assert np.array_equal(to_host(out), ref)
     assert capi.rhs_release() == 2
+
+
+# ------------------------------------------------ reduced full-step configs
+_REDUCED = {}
+
+
+def _reduced_case(orc, name):
+    """Start states of the reduced full-step configurations (built by the
+    oracle only, cached for the module):
+      turb64_contact   -- 64^3 periodic turbulence with a density/energy jump
+                          over half the box (four z chunks, twenty column
+                          tiles per chunk, many correction-list regions);
+      turb64_developed -- the same field after 50 oracle steps, when shocklets
+                          have formed (2-9 % of the face-fields per direction
+                          take the WENO branch);
+      quad512          -- 2D four-quadrant 512^2 (the face-once correction
+                          kernels of grids of 131072 cells or more)."""
+    if name not in _REDUCED:
+        if name.startswith("turb64"):
+            U, dx = _turb_jump(64, 64, 64, 5)
+            bc = [0] * 6
+            if name == "turb64_developed":
+                po = orc.params(64, 64, 64, dx, bc=bc)
+                for _ in range(50):
+                    _, st = orc.step(U, dx, G, po)
+                    assert st == 0
+        else:
+            U, dx, _ = w.four_quadrant_2d(512, 512, 7)
+            bc = [1] * 6
+        _REDUCED[name] = (np.ascontiguousarray(U), dx, bc)
+    U, dx, bc = _REDUCED[name]
+    return U.copy(), dx, bc
+
+
+@pytest.mark.parametrize("name", ["turb64_contact", "turb64_developed", "quad512"])
+def test_reduced_config_hundred_steps(orc, capi, name):
+    """100 steps of the default hybrid scheme through weno_l2is_advance (the
+    benchmark's launch sequence: device CFL dt, folded CFL maximum, list
+    corrections) against 100 oracle steps: the state to 1e-10 and the clock
+    to round-off; the switch flags of the start state bit-exact outside the
+    1e-12 eps band (near-threshold faces counted)."""
+    import torch
+    say(f"[reduced 100 steps] {name}")
+    U, dx, bc = _reduced_case(orc, name)
+    shape = shape_of(U)
+    dim = 1 + (shape[1] > 1) + (shape[2] > 1)
+    po, pg = params_pair(orc, capi, shape, dx, bc=bc)
+    ctx = capi.Context(*shape, dx, G, pg)
+    Ud = to_dev(U)
+    weno = []
+    for d in range(dim):
+        fo, so = orc.face_debug(U, dx, G, po, d)
+        fl = torch.zeros(fo.size, dtype=torch.uint8, device="cuda")
+        sg = torch.zeros(fo.size, dtype=torch.float64, device="cuda")
+        ctx.face_debug(Ud, d, fl, sg)
+        torch.cuda.synchronize()
+        fg = to_host(fl).reshape(fo.shape)
+        eps = po.thr_C * (dx / po.thr_L[d]) ** po.thr_alpha
+        near = np.abs(so - eps) <= 1e-12 * eps
+        mism = (fg != fo) & ~near
+        weno.append(float((fo == 0).mean()))
+        say(f"    dir={d} WENO face-fields={weno[-1]:.4f} near_threshold={int(near.sum())}"
+            f" flag_mismatch={int(mism.sum())}")
+        assert mism.sum() == 0
+    assert max(weno) > (0.01 if name != "quad512" else 0.005)
+    Uo = U.copy()
+    t_o = 0.0
+    for _ in range(100):
+        dt, st = orc.step(Uo, dx, G, po)
+        assert st == 0
+        t_o += dt
+    ctx.set_time(0.0)
+    ctx.advance(Ud, 100, 1e300)
+    t_g, _, k = ctx.clock()
+    stg = ctx.status()
+    ctx.close()
+    torch.cuda.synchronize()
+    got = to_host(Ud)
+    err = z20(got, Uo)
+    say(f"    100 steps: t oracle={t_o!r} gpu={t_g!r} z20={err:.3e}")
+    assert stg == 0 and k == 100
+    assert abs(t_g - t_o) <= 1e-12 * t_o
+    assert err <= 1e-10

@@ -63,6 +63,10 @@ MUTANTS = [
     ("llf_two_cells", "face.c",
      "for (m = 0; m < 6; ++m) {\n        double e = fabs(cell_eig(",
      "for (m = 2; m < 4; ++m) {\n        double e = fabs(cell_eig("),
+    # the second term of beta_01 (Eq.(15)) with a wrong coefficient
+    ("beta01_coefficient", "weno_scalar.c",
+     "b01 = 13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2;",
+     "b01 = 13.0 / 12.0 * t1 * t1 + 0.5 * t2 * t2;"),
     # time step from the largest single-direction speed instead of the sum
     ("cfl_max_over_directions", "solver.c",
      "for (d = 0; d < g->dim; ++d) s += fabs(prim[1 + d]) + prim[5];\n    if (s > smax || s != s)",

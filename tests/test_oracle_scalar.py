@@ -162,3 +162,78 @@ def test_fifth_order_on_smooth_data(orc, lam):
         errs.append(abs(f - np.sin(x0 + 0.5 * h)))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert min(rates) > 4.6, rates
+
+
+# ------------------------------------------ comparison weights (Sec. 2.2, 2.4)
+W_IS, W_IS_B01 = 1, 2
+
+
+def beta01_quadrature(a):
+    """Eq.(9) on the 3-point stencil S01 = {j-1, j, j+1}: the first and
+    second derivative integrals of its quadratic reconstruction."""
+    P = recon_poly(S01, sub(a, S01))
+    return sum(np.sum(GW * P.deriv(l)(GX) ** 2) for l in (1, 2))
+
+
+@pytest.mark.parametrize("weights", [W_IS, W_IS_B01])
+def test_comparison_weights_from_the_integral_definitions(orc, weights):
+    """Eq.(8) (and with Eq.(14) the beta_01 factor on the two 2-point
+    stencils) evaluated from the quadrature-based beta_k, tau_5 and beta_01:
+    the weights and the flux of the oracle agree."""
+    eps = 1e-20
+    for a in draws(120, 31):
+        q, beta, tau5, _ = ref_quantities(a)
+        r = tau5 / (beta + eps)
+        if weights == W_IS_B01:
+            r01 = tau5 / (beta01_quadrature(a) + eps)
+            r[:2] *= r01
+        alpha = D * (1.0 + r)
+        om = alpha / alpha.sum()
+        f, dbg = orc.weno(a, weights, 0.0, eps)
+        np.testing.assert_allclose(dbg["omega"], om, rtol=1e-9, atol=1e-13)
+        assert abs(f - om @ q) <= 1e-10 * (1 + np.abs(a).max())
+        assert np.all(dbg["omega"] >= 0) and abs(dbg["omega"].sum() - 1) <= 8.9e-16
+
+
+def test_original_weights_are_the_large_lambda_limit(orc):
+    """Two code paths of the oracle: Eq.(28) with lambda -> infinity equals
+    Eq.(8) (E_k and eps drop out where beta_k is not tiny)."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        a = rng.standard_normal(5)
+        _, d1 = orc.weno(a, W_IS, 0.0, 1e-20)
+        if d1["beta"].min() < 1e-6:
+            continue
+        _, d2 = orc.weno(a, 0, 1e200, 1e-20)
+        np.testing.assert_allclose(d1["omega"], d2["omega"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("weights", [W_IS, W_IS_B01])
+def test_comparison_weights_fifth_order_on_smooth_data(orc, weights):
+    """Away from critical points tau5 / beta_k = O(dx^4) (Eq.(13)), so the
+    reconstruction keeps fifth order."""
+    errs = []
+    for h in [0.1 / 2 ** k for k in range(4)]:
+        x0 = 0.37
+        a = [(np.cos(x0 + (o - 0.5) * h) - np.cos(x0 + (o + 0.5) * h)) / h for o in range(-2, 3)]
+        f, _ = orc.weno(a, weights)
+        errs.append(abs(f - np.sin(x0 + 0.5 * h)))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(rates) > 4.6, rates
+
+
+def test_beta01_weights_favour_two_point_stencils_next_to_a_shock(orc):
+    """The case of Eq.(14a) in Sec. 2.4: a jump inside S3 only, smooth data in
+    S0, S1, S2.  tau5 = O(1) while beta_0, beta_1, beta_01, beta_2 are small,
+    so the product of Eq.(14) gives the 2-point stencils far more weight,
+    relative to their optimal weights, than the 3-point stencil S2; the
+    original Eq.(8) weights do not."""
+    h = 0.01
+    smooth = [np.sin(1.0 + o * h) for o in range(-2, 3)]
+    a = np.array(smooth)
+    a[0] += 1.0  # the jump between f_{j-2} and f_{j-1}
+    _, db = orc.weno(a, W_IS_B01)
+    _, di = orc.weno(a, W_IS)
+    rel_b = (db["omega"][0] / D[0]) / (db["omega"][2] / D[2])
+    rel_i = (di["omega"][0] / D[0]) / (di["omega"][2] / D[2])
+    assert rel_b > 1e3 * rel_i and rel_b > 1e3, (rel_b, rel_i)

@@ -76,9 +76,9 @@ def test_sod_shock_position(orc):
     assert abs(x[i] + 0.5 * dx - xs) < 2 * dx
 
 
-def _advect(orc, n, t_end, hybrid, dt=None):
+def _advect(orc, n, t_end, hybrid, dt=None, weights=0):
     U, dx = w.smooth_advection(n)
-    p = orc.params(n, 1, 1, dx, hybrid=hybrid, bc=[0, 0, 1, 1, 1, 1])
+    p = orc.params(n, 1, 1, dx, hybrid=hybrid, bc=[0, 0, 1, 1, 1, 1], weights=weights)
     if dt is None:
         # dt ~ dx^(5/3) keeps the RK3 error below the spatial error
         dt0 = 0.5 * (2.0 / 32) / (1.0 + np.sqrt(G))
@@ -106,6 +106,25 @@ def test_design_order_smooth_advection(orc, hybrid, min_rate):
         errs.append(np.mean(np.abs(U[0] - ex[0])))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(len(ns) - 1)]
     assert rates[-1] > min_rate and rates[-2] > min_rate, (errs, rates)
+
+
+def test_comparison_weights_on_smooth_advection(orc):
+    """Pure WENO with the original WENO-IS weights of Eq.(8) loses order on
+    the smooth wave (its extrema are critical points: the 2-point stencils
+    get too much weight, Sec. 2.4), converging at ~2.2 for N = 64..256; the
+    beta_01 factor of Eq.(14)-(15) leaves that regime by N = 128 (errors
+    1.0e-3, 1.6e-7, 4.7e-10 at N = 64, 128, 256)."""
+    ns = [64, 128, 256]
+    errs = {}
+    for wts in (1, 2):
+        errs[wts] = []
+        for n in ns:
+            U = _advect(orc, n, 2.0, 2, weights=wts)
+            ex = w.smooth_advection_exact(n, 2.0)
+            errs[wts].append(np.mean(np.abs(U[0] - ex[0])))
+    rates = [np.log2(errs[1][i] / errs[1][i + 1]) for i in range(2)]
+    assert max(rates) < 3.0, (errs, rates)
+    assert errs[2][-1] < 1e-8 and errs[2][-1] < 1e-4 * errs[1][-1], errs
 
 
 def test_hybrid_is_linear_everywhere_on_smooth_advection(orc):
