@@ -107,9 +107,12 @@ int weno_l2is_params_default(weno_l2is_params *p, int nx, int ny, int nz,
  * the two RK stage buffers, one accumulator (per-direction path), the
  * correction list (8 bytes per cell), a 4.4 KB control block, for 2D
  * grids of 131072 cells or more the face-once correction buffers (68 bytes
- * per cell), and for 3D grids with every face WENO (WL2_HYB_WENO_ONLY, LLF
- * splitting) a face buffer (120 bytes per cell).  About 2.2 GB for a 256^3
- * grid (4.2 GB with every face WENO). */
+ * per cell), and for 3D grids a face buffer (120 bytes per cell) where the
+ * corrections compute each face once: with every face WENO (LLF
+ * splitting), and with the hybrid switch (per field or per face), which
+ * also lists the faces that need the WENO flux (12 bytes per cell).  About
+ * 4.4 GB for a 256^3 grid with the hybrid switch (4.2 GB with every face
+ * WENO, 2.2 GB with every face linear). */
 int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma,
                      const weno_l2is_params *p, void *hip_stream,
                      weno_l2is_ctx **out);
@@ -209,7 +212,7 @@ int weno_l2is_status(weno_l2is_ctx *ctx, unsigned *status_bits, int clear);
  * WL2_PATH_FUSED_CELLS (the fused stage kernel with the nonlinear
  * corrections computed per listed cell even where the default corrects
  * each flagged face once: 2D grids of 131072 cells or more, and 3D grids
- * with every face WENO).
+ * with every face WENO or the hybrid switch).
  * zchunk: z planes (3D) or rows (2D, at most 62) per work item of the fused
  * kernels (0 = automatic).  waves_per_simd: register budget of the 3D fused
  * kernel, 1 or 2 (0 = default 2).  The sweeps agree with the fused kernels

@@ -35,7 +35,8 @@ struct weno_l2is_ctx {
   unsigned long long* list;  // cells next to faces needing the WENO flux (fused kernels)
   double* fo_D = nullptr;          // 2D face-once corrections: face changes per list entry
   unsigned int* fo_map = nullptr;  // and the cell -> list entry map (null: per-cell kernel)
-  double* fo3 = nullptr;           // 3D, every face WENO: each face's change (face-once)
+  double* fo3 = nullptr;           // 3D: each face's change (face-once corrections)
+  unsigned int* flist = nullptr;   // 3D hybrid: faces needing the WENO flux
   unsigned int* counts = nullptr;  // 3D: entries each stage-kernel workgroup listed
   double* inflow = nullptr;        // x- inflow side: ghost state [nvar][ny*nz]
   bool inflow_set = false;         // weno_l2is_set_inflow has been called
@@ -322,8 +323,12 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
   L.zc = fused_zchunk(c);
   L.wpe = c->wpe;  // the scheme's build is chosen from L.ph
   L.fo3 = c->path == WL2_PATH_FUSED_CELLS ? nullptr : c->fo3;
+  L.flist = c->path == WL2_PATH_FUSED_CELLS ? nullptr : c->flist;
+  const size_t ce = fused3d_count_entries(c->n);
   L.counts = c->counts;
-  L.offs = c->counts ? c->counts + fused3d_count_entries(c->n) : nullptr;
+  L.offs = c->counts ? c->counts + ce : nullptr;
+  L.counts_f = c->counts ? c->counts + 2 * ce + 1 : nullptr;
+  L.offs_f = c->counts ? c->counts + 5 * ce + 1 : nullptr;
   for (int d = 0; d < 3; ++d) L.n[d] = c->n[d];
   L.g = c->g;
   L.ph = c->ph;
@@ -437,16 +442,22 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
          hipMalloc(&c->fo_map, sizeof(unsigned int) * (size_t)c->ncell) == hipSuccess &&
          // every map value stays a valid entry index (< ncell) from the start
          hipMemsetAsync(c->fo_map, 0, sizeof(unsigned int) * (size_t)c->ncell, c->stream) == hipSuccess;
-  // 3D with every face WENO (LLF splitting): the corrections compute each
-  // face once into a face buffer (15 doubles per cell)
-  if (ok && c->dim == 3 && p->hybrid == WL2_HYB_WENO_ONLY && p->split == WL2_SPLIT_LLF)
+  // 3D: the corrections compute each face once into a face buffer (15
+  // doubles per cell): every face with every face WENO (LLF splitting), the
+  // faces of the face lists (3 entries per cell) with the hybrid switch
+  const bool hyb3 = c->dim == 3 && (p->hybrid == WL2_HYB_PER_FIELD || p->hybrid == WL2_HYB_PER_FACE);
+  if (ok && c->dim == 3 && ((p->hybrid == WL2_HYB_WENO_ONLY && p->split == WL2_SPLIT_LLF) || hyb3))
     ok = hipMalloc(&c->fo3, sizeof(double) * fused3d_face_doubles(c->n)) == hipSuccess;
+  if (ok && hyb3)
+    ok = hipMalloc(&c->flist, sizeof(unsigned int) * fused3d_flist_entries(c->n)) == hipSuccess;
   // 3D: per-workgroup counts of the correction list and their prefix sums
   if (ok && p->bc[0] == WL2_BC_INFLOW)
     ok = hipMalloc(&c->inflow, sizeof(double) * c->nvar * (size_t)ny * nz) == hipSuccess;
   if (ok) c->g.inflow = c->inflow;
+  // (cell list: counts and offsets; face lists: counts and offsets over
+  // three directions)
   if (ok && c->dim == 3)
-    ok = hipMalloc(&c->counts, sizeof(unsigned int) * (2 * fused3d_count_entries(c->n) + 1)) ==
+    ok = hipMalloc(&c->counts, sizeof(unsigned int) * (8 * fused3d_count_entries(c->n) + 2)) ==
          hipSuccess;
   if (ok) ok = hipMemsetAsync(c->ctl, 0, sizeof(StepCtl), c->stream) == hipSuccess;
   if (!ok) {
@@ -457,6 +468,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
     (void)hipFree(c->fo_D);
     (void)hipFree(c->fo_map);
     (void)hipFree(c->fo3);
+    (void)hipFree(c->flist);
     (void)hipFree(c->counts);
     (void)hipFree(c->inflow);
     (void)hipFree(c->ctl);
@@ -479,6 +491,7 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   (void)hipFree(c->fo_D);
   (void)hipFree(c->fo_map);
   (void)hipFree(c->fo3);
+  (void)hipFree(c->flist);
   (void)hipFree(c->counts);
   (void)hipFree(c->inflow);
   (void)hipFree(c->ctl);

@@ -14,8 +14,12 @@
 // Physical fluxes along the face direction are formed on the fly from the
 // light record.  Every face takes the linear branch here; a cell next to a
 // face whose detector asks for the nonlinear flux is appended (with its
-// face mask) to a correction list, and weno_fix3d_kernel adds the
-// difference of the WENO-L2IS flux afterwards.
+// face mask) to a correction list, and the face itself to the face list of
+// its direction.  The correction kernels then compute each listed face's
+// change (WENO-L2IS minus linear) once (weno_flist3d_kernel) and add the
+// changes of each listed cell's faces in a fixed order
+// (weno_sumlist3d_kernel); weno_fix3d_kernel is the per-cell form, which
+// computes each face for both of its cells.
 // Tiles are numbered so that the workgroups resident on one XCD (dispatch is
 // round-robin over the 8 XCDs) take a contiguous range of tiles and share
 // their halos in that XCD's L2.  A tile at the high x or y edge of the grid
@@ -60,6 +64,17 @@ struct FusedArgs {
   unsigned int* offs;        // exclusive prefix sums of counts (nreg + 1 values)
   StepCtl* cfl;              // RK: if set, fold the CFL speed of the new state
                              // into cfl->smax / status (next step's dt)
+  // face lists (or null: per-cell corrections): the faces that need the
+  // WENO flux, the x, y and z lists back to back, each cut into one region
+  // per workgroup as the cell list is.  An entry locates its face inside
+  // the workgroup's tile: slot + 256 * (plane - z0), with slot = row * 17 +
+  // fx for an x face (fx = 0 at the tile's x0 - 1/2), fy * 16 + col for a y
+  // face and oy * 16 + ox for a z face, whose plane is the index of the face
+  // (between cells plane - 1 and plane).
+  unsigned int* flist;
+  unsigned int* counts_f;    // faces each workgroup listed, [direction][region]
+  unsigned int* offs_f;      // their exclusive prefix sums over (direction, region)
+  double* D;                 // face changes: x, y, z faces, 5 values each, [v][face]
 };
 
 // The correction list is cut into one region per workgroup of the stage
@@ -80,6 +95,53 @@ __device__ __forceinline__ long long list_region_start(const FusedArgs& a, const
   const long long vr = min(FT_Y, g.n[1] - tty * FT_Y);
   return (long long)g.n[0] * g.n[1] * z0 +
          ((long long)tty * FT_Y * g.n[0] + (long long)ttx * FT_X * vr) * planes;
+}
+
+// First index of the face-list region of direction d of logical tile r,
+// counted from the start of the x list.  Each workgroup lists the faces it
+// owns: along x the faces x0 .. x0 + cols - 1 of each of its rows, and in
+// the last tile along x also the last face of the row; along y alike; along
+// z the faces z0 + 1 .. z1 of each column, and in the first z chunk also
+// face 0.  So the regions of a direction tile [0, faces of that direction)
+// in logical tile order, and every region before a given one is full-sized
+// where it matters (as for the cell list).
+__device__ __forceinline__ long long flist_region_start(const FusedArgs& a, const KGrid& g, int d,
+                                                        int r) {
+  const int ttx = r % a.tiles_x, rest = r / a.tiles_x;
+  const int tty = rest % a.tiles_y, tzc = rest / a.tiles_y;
+  const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const long long z0 = (long long)tzc * a.zc;
+  const long long planes = min((long long)a.zc, nz - z0);
+  const long long rows = min((long long)FT_Y, ny - (long long)tty * FT_Y);
+  if (d == 0)
+    return (nx + 1) * ny * z0 + ((long long)tty * FT_Y * (nx + 1) + (long long)ttx * FT_X * rows) * planes;
+  const long long nfx = (nx + 1) * ny * nz;
+  if (d == 1) {
+    const long long rowsy = rows + (tty == a.tiles_y - 1 ? 1 : 0);
+    return nfx + nx * (ny + 1) * z0 + ((long long)tty * FT_Y * nx + (long long)ttx * FT_X * rowsy) * planes;
+  }
+  const long long nfy = nx * (ny + 1) * nz;
+  const long long planesz = planes + (tzc == 0 ? 1 : 0);
+  return nfx + nfy + nx * ny * (z0 + (tzc > 0 ? 1 : 0)) +
+         ((long long)tty * FT_Y * nx + (long long)ttx * FT_X * rows) * planesz;
+}
+
+// The faces of the owner's cell (ox, oy, plane z0 + pl) flagged in its mask
+// m (x-, x+, y-, y+, z-, z+) that this workgroup lists: every flagged face
+// below the cell along x and y, the one above along z, and the faces above
+// along x (y) in the last tile along x (y) and below along z in plane 0,
+// which no other cell of a workgroup lists.  Entries as in FusedArgs::flist.
+__device__ __forceinline__ void list_faces(const FusedArgs& a, unsigned int* const (&fl)[3],
+                                           unsigned int* cnt, unsigned m, int t, int ox, int oy, int pl,
+                                           bool plane0, bool last_x, bool last_y) {
+  const unsigned int p = 256u * (unsigned)pl;
+  const unsigned int sx = (unsigned)(oy * (FT_X + 1) + ox);
+  if (m & 1u) fl[0][atomicAdd(&cnt[0], 1u)] = sx + p;
+  if ((m & 2u) && last_x) fl[0][atomicAdd(&cnt[0], 1u)] = sx + 1u + p;
+  if (m & 4u) fl[1][atomicAdd(&cnt[1], 1u)] = (unsigned)t + p;
+  if ((m & 8u) && last_y) fl[1][atomicAdd(&cnt[1], 1u)] = (unsigned)(t + FT_X) + p;
+  if (m & 32u) fl[2][atomicAdd(&cnt[2], 1u)] = (unsigned)t + p + 256u;
+  if ((m & 16u) && plane0) fl[2][atomicAdd(&cnt[2], 1u)] = (unsigned)t;
 }
 
 typedef __attribute__((address_space(3))) double lds_wdouble;
@@ -226,7 +288,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   __shared__ double sfy[NV][NYF];            // y-face fluxes of plane z
   __shared__ double2 swin[2 * RING_SLOT];    // two oldest cells of each z window
   __shared__ unsigned char sgx[NXF], sgy[NYF];  // face needs the nonlinear flux
+  __shared__ unsigned char scm[FT_OWN];          // face mask of the owner's last cell
   __shared__ unsigned int s_cnt;                 // entries listed by this workgroup
+  __shared__ unsigned int s_fcnt[3];             // faces listed per direction
+  __shared__ unsigned int s_any[2];              // plane z - 1 has faces to list: s_any[z & 1]
 
   double dt = 0.0;
   if (OUT == OUT_RK) {
@@ -265,7 +330,21 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
   // LDS and stored at the end; made visible by the barriers of the first
   // plane before any append)
   const long long reg0 = list_region_start(a, g, logical);
-  if (t == 0) s_cnt = 0u;
+  // face lists: this workgroup's region of each direction's list
+  const bool flists = HYB != HYB_WENO_ONLY && HYB != HYB_LINEAR_ONLY && a.flist != nullptr;
+  unsigned int* fl[3] = {nullptr, nullptr, nullptr};
+  if (flists) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fl[d] = a.flist + flist_region_start(a, g, d, logical);
+  }
+  if (t == 0) {
+    s_cnt = 0u;
+    s_fcnt[0] = 0u;
+    s_fcnt[1] = 0u;
+    s_fcnt[2] = 0u;
+    s_any[0] = 0u;
+    s_any[1] = 0u;
+  }
 
   // halo cell of this thread (t < NHALO): tile-relative (hc, hr)
   int hc = 0, hr = 0;
@@ -361,6 +440,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       load_col_raw<NV>(a.Uk, g, hcol, z + 1, hpre);
     }
     __syncthreads();
+    // the next plane's flag starts clear (its last reader, the previous
+    // plane's append point, is behind this barrier; its first writer comes
+    // after this plane's second one)
+    if (flists && t == 0) s_any[(z + 1) & 1] = 0u;
     __builtin_amdgcn_s_setprio(0);  // face rounds at normal priority
     __builtin_amdgcn_sched_barrier(0);
     // x faces: thread t < 255 -> row t/17, face fx = t%17 at x0 + fx - 1/2
@@ -389,6 +472,14 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
     // 1.2-1.7 % faster at 256^3; a wave's priority is local to this kernel)
     __builtin_amdgcn_s_setprio(2);
     __builtin_amdgcn_sched_barrier(0);
+    if (flists && z > z0 && s_any[z & 1]) {
+      // the faces of the previous plane's cells that need the WENO flux go
+      // to the face lists (from the cell masks kept in LDS, here where few
+      // registers are live; only in planes where some cell had a mask)
+      if (valid) list_faces(a, fl, s_fcnt, scm[t], t, ox, oy, z - 1 - z0, z - 1 == 0,
+                            ox == cols_v - 1 && ttx == a.tiles_x - 1,
+                            oy == rows_v - 1 && tty == a.tiles_y - 1);
+    }
     if (valid) {
       // z face z + 1/2: cells z-2, z-1 (ring), z .. z+3 (registers)
       double Fz[NV];
@@ -413,7 +504,10 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
           const int lane = threadIdx.x & 63;
           const int leader = __ffsll((long long)ball) - 1;
           unsigned int basei = 0;
-          if (lane == leader) basei = atomicAdd(&s_cnt, (unsigned int)__popcll(ball));
+          if (lane == leader) {
+            basei = atomicAdd(&s_cnt, (unsigned int)__popcll(ball));
+            if (flists) s_any[(z + 1) & 1] = 1u;
+          }
           basei = __shfl(basei, leader, 64);
           if (cm) {
             const unsigned int rank = __popcll(ball & ((1ull << lane) - 1ull));
@@ -445,13 +539,61 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fzp[v] = Fz[v];
+      // the z faces of the cell (bit 0: z - 1/2, bit 1: z + 1/2), listed at
+      // the next plane's append point (kept in LDS, not in registers)
+      if (flists) scm[t] = (unsigned char)cm;
     }
   }
   if (HYB != HYB_WENO_ONLY) {
+    if (flists && z1 > z0) {
+      __syncthreads();  // the last plane's masks and flag
+      if (valid && s_any[z1 & 1])
+        list_faces(a, fl, s_fcnt, scm[t], t, ox, oy, z1 - 1 - z0, z1 - 1 == 0,
+                   ox == cols_v - 1 && ttx == a.tiles_x - 1, oy == rows_v - 1 && tty == a.tiles_y - 1);
+    }
     __syncthreads();  // every append of the workgroup is counted
     if (t == 0) a.counts[logical] = s_cnt;
+    if (flists && t < 3) a.counts_f[t * (int)gridDim.x + logical] = s_fcnt[t];
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
+}
+
+// Exclusive prefix sums of counts[0 .. n) into soffs[0 .. n] (LDS), by one
+// block: each thread sums a contiguous run, the run sums are scanned
+// (Hillis-Steele over at most 256 threads), then each run is written.
+__device__ __forceinline__ void block_offsets(const unsigned int* counts, int n, unsigned int* soffs,
+                                              unsigned int* spart) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (n + nt - 1) / nt;
+  const int b = t * per, e = min(b + per, n);
+  unsigned int sum = 0u;
+  for (int r = b; r < e; ++r) sum += counts[r];
+  spart[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < nt; d <<= 1) {
+    const unsigned int v = t >= d ? spart[t - d] : 0u;
+    __syncthreads();
+    spart[t] += v;
+    __syncthreads();
+  }
+  unsigned int run = t > 0 ? spart[t - 1] : 0u;
+  for (int r = b; r < e; ++r) {
+    soffs[r] = run;
+    run += counts[r];
+  }
+  if (t == nt - 1) soffs[n] = spart[nt - 1];
+  __syncthreads();
+}
+
+// Index of the segment holding entry i: offs[lo] <= i < offs[lo + 1].
+__device__ __forceinline__ int find_segment(const unsigned int* offs, int nseg, unsigned int i) {
+  int lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
 // Per listed cell: add the nonlinear part of the flux of its flagged faces,
@@ -523,26 +665,7 @@ __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g
     __shared__ unsigned int spart[128];
     const unsigned int* offs = a.offs;
     if (nreg <= SCAN_LDS) {
-      const int t = threadIdx.x, nt = blockDim.x;  // 128
-      const int per = (nreg + nt - 1) / nt;
-      const int b = t * per, e = min(b + per, nreg);
-      unsigned int sum = 0u;
-      for (int r = b; r < e; ++r) sum += a.counts[r];
-      spart[t] = sum;
-      __syncthreads();
-      for (int d = 1; d < nt; d <<= 1) {
-        const unsigned int v = t >= d ? spart[t - d] : 0u;
-        __syncthreads();
-        spart[t] += v;
-        __syncthreads();
-      }
-      unsigned int run = t > 0 ? spart[t - 1] : 0u;
-      for (int r = b; r < e; ++r) {
-        soffs[r] = run;
-        run += a.counts[r];
-      }
-      if (t == nt - 1) soffs[nreg] = spart[nt - 1];
-      __syncthreads();
+      block_offsets(a.counts, nreg, soffs, spart);
       offs = soffs;
     }
     const unsigned int n = offs[nreg];
@@ -551,13 +674,134 @@ __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g
     const bool grouped = n <= threads / GRP;
     const unsigned int step = grouped ? threads / GRP : threads;
     for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step) {
-      int lo = 0, hi = nreg;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (offs[mid] <= i) lo = mid;
-        else hi = mid;
-      }
+      const int lo = find_segment(offs, nreg, i);
       fix_one(a.list[list_region_start(a, g, lo) + (i - offs[lo])], grouped);
+    }
+  }
+  if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
+}
+
+// Face lists, face-once corrections: every entry of the three face lists
+// (taken as one index space over (direction, region), the offsets in LDS or
+// written by list_scan_kernel) gives one face, whose change of flux (WENO
+// minus linear, Eq.(20)-(28), (33)) goes to D[v][face] of its direction.
+// One face per lane, and the lanes of a wavefront take consecutive entries,
+// so that a wavefront runs faces of one direction (except where the x list
+// meets the y list and the y list the z list).  The change depends on the
+// face only: the same bits as weno_fix3d_kernel computes for either cell.
+template <int OUT, int SPLIT, int HYB>
+__global__ __launch_bounds__(128, 2) void weno_flist3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
+  constexpr int NV = 5;
+  if (OUT == OUT_RK && !(a.ctl->dt > 0.0)) return;
+  const int nreg = a.tiles_x * a.tiles_y * ((g.n[2] + a.zc - 1) / a.zc);
+  const int nseg = 3 * nreg;
+  __shared__ unsigned int soffs[SCAN_LDS + 1];
+  __shared__ unsigned int spart[128];
+  const unsigned int* offs = a.offs_f;
+  if (nseg <= SCAN_LDS) {
+    block_offsets(a.counts_f, nseg, soffs, spart);
+    offs = soffs;
+  }
+  const unsigned int n = offs[nseg];
+  const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
+  const unsigned int threads = gridDim.x * blockDim.x;
+  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += threads) {
+    const int seg = find_segment(offs, nseg, i);
+    const int d = seg / nreg, r = seg - d * nreg;
+    const unsigned int e = a.flist[flist_region_start(a, g, d, r) + (i - offs[seg])];
+    // the face from the tile of region r and the entry's slot and plane
+    const int ttx = r % a.tiles_x, rest = r / a.tiles_x;
+    const int tty = rest % a.tiles_y, tzc = rest / a.tiles_y;
+    const int slot = (int)(e & 255u);
+    const int z = tzc * a.zc + (int)(e >> 8);
+    const int w = d == 0 ? FT_X + 1 : FT_X;
+    const int x = ttx * FT_X + slot % w;
+    const int y = tty * FT_Y + slot / w;
+    const long long ex = nx + (d == 0), ey = ny + (d == 1);
+    const long long f = x + ex * (y + ey * (long long)z);
+    double dF[NV];
+    double* D;
+    long long nf;
+    if (d == 0) {
+      face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, z, 0, dF);
+      D = a.D;
+      nf = nfx;
+    } else if (d == 1) {
+      face_delta<NV, 1, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, z, 0, dF);
+      D = a.D + 5 * nfx;
+      nf = nfy;
+    } else {
+      face_delta<NV, 2, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[2], x, y, z, 0, dF);
+      D = a.D + 5 * (nfx + nfy);
+      nf = nfz;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) D[v * nf + (long long)f] = dF[v];
+  }
+}
+
+// Face lists, per listed cell: the changes of its flagged faces read from D
+// and summed in the fixed order x-, x+, y-, y+, z-, z+ (+ below, - above),
+// then added to the output exactly as weno_fix3d_kernel adds them (the same
+// bits); with a.cfl set the CFL speed of the corrected cell is folded; the
+// next stage's list counter is cleared.
+template <int OUT>
+__global__ __launch_bounds__(256) void weno_sumlist3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
+  constexpr int NV = 5;
+  if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
+  double scale = 1.0;
+  if (OUT == OUT_RK) {
+    const double dt = a.ctl->dt;
+    if (!(dt > 0.0)) return;
+    scale = a.rk_b * dt;
+  }
+  const int nreg = a.tiles_x * a.tiles_y * ((g.n[2] + a.zc - 1) / a.zc);
+  __shared__ unsigned int soffs[SCAN_LDS + 1];
+  __shared__ unsigned int spart[256];
+  const unsigned int* offs = a.offs;
+  if (nreg <= SCAN_LDS) {
+    block_offsets(a.counts, nreg, soffs, spart);
+    offs = soffs;
+  }
+  const unsigned int n = offs[nreg];
+  const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
+  const double* Dd[3] = {a.D, a.D + 5 * nfx, a.D + 5 * (nfx + nfy)};
+  const long long nf[3] = {nfx, nfy, nfz};
+  double cfl_max = 0.0;
+  bool cfl_bad = false;
+  const unsigned int threads = gridDim.x * blockDim.x;
+  for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += threads) {
+    const int lo = find_segment(offs, nreg, i);
+    const unsigned long long e = a.list[list_region_start(a, g, lo) + (i - offs[lo])];
+    const long long c = (long long)(e >> 8);
+    const unsigned cm = (unsigned)(e & 0xffu);
+    const long long x = c % nx, y = (c / nx) % ny, z = c / (nx * ny);
+    // the face below the cell along each direction (the one above is next)
+    const long long lof[3] = {x + (nx + 1) * (y + ny * z), x + nx * (y + (ny + 1) * z), c};
+    const long long step[3] = {1, nx, nx * ny};
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      if (!((cm >> f) & 1u)) continue;
+      const int dir = f >> 1;
+      const long long idx = lof[dir] + ((f & 1) ? step[dir] : 0);
+      const double sg = (f & 1) ? -1.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sg * Dd[dir][v * nf[dir] + idx];
+    }
+    double un[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      un[v] = a.out[v * g.ncell + c] + scale * (acc[v] * ph.inv_dx);
+      a.out[v * g.ncell + c] = un[v];
+    }
+    if (OUT == OUT_RK && a.cfl != nullptr) {
+      const double m[3] = {un[1], un[2], un[3]};
+      cfl_max = nan_max(cfl_max, cfl_speed<3>(un[0], m, un[4], ph.gamma, cfl_bad));
     }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);

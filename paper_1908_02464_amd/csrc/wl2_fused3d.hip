@@ -23,6 +23,10 @@ FusedArgs make_args(const FusedLaunch& L) {
   a.counts = L.counts;
   a.offs = L.offs;
   a.cfl = L.out_kind == OUT_RK ? L.cfl : nullptr;
+  a.flist = L.flist;
+  a.counts_f = L.counts_f;
+  a.offs_f = L.offs_f;
+  a.D = L.fo3;
   a.tiles_x = (L.n[0] + FT_X - 1) / FT_X;
   a.tiles_y = (L.n[1] + FT_Y - 1) / FT_Y;
   return a;
@@ -105,12 +109,34 @@ static hipError_t fix_face_once(const FusedLaunch& L, const FusedArgs& a) {
   return hipGetLastError();
 }
 
+// Face lists: each listed face's change once into the face buffer (one
+// launch for the three lists), then the listed cells' sums.
+template <int O>
+static hipError_t fix_face_lists(const FusedLaunch& L, const FusedArgs& a) {
+  const int sp = L.ph.split, hy = L.ph.hybrid;
+  const int nreg = a.tiles_x * a.tiles_y * ((L.n[2] + a.zc - 1) / a.zc);
+  if (3 * nreg > SCAN_LDS)
+    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts_f, 3 * nreg, a.offs_f);
+  if (nreg > SCAN_LDS)
+    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts, nreg, a.offs);
+#define WL2_FL(S, H) \
+  hipLaunchKernelGGL((weno_flist3d_kernel<O, S, H>), dim3(1024), dim3(128), 0, L.stream, a, L.g, L.ph)
+  if (sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FL(SPLIT_LLF, HYB_PER_FIELD);
+  else if (sp == SPLIT_ROE && hy == HYB_PER_FIELD) WL2_FL(SPLIT_ROE, HYB_PER_FIELD);
+  else WL2_FL(-1, -1);
+#undef WL2_FL
+  hipLaunchKernelGGL((weno_sumlist3d_kernel<O>), dim3(1024), dim3(256), 0, L.stream, a, L.g, L.ph);
+  return hipGetLastError();
+}
+
 hipError_t fused3d_fix(const FusedLaunch& L) {
   const FusedArgs a = make_args(L);
   const dim3 fg(1024), fb(128);
   const int sp = L.ph.split, hy = L.ph.hybrid;
   if (L.fo3 != nullptr && sp == SPLIT_LLF && hy == HYB_WENO_ONLY)
     return L.out_kind == OUT_RK ? fix_face_once<OUT_RK>(L, a) : fix_face_once<OUT_WRITE>(L, a);
+  if (L.fo3 != nullptr && L.flist != nullptr && hy != HYB_WENO_ONLY)
+    return L.out_kind == OUT_RK ? fix_face_lists<OUT_RK>(L, a) : fix_face_lists<OUT_WRITE>(L, a);
   if (!(sp == SPLIT_LLF && hy == HYB_WENO_ONLY)) {
     // offsets of the per-workgroup list regions (the dense form needs none;
     // up to SCAN_LDS regions the correction kernel forms them itself)

@@ -27,8 +27,12 @@ struct FusedLaunch {
   int out_kind;  // OUT_WRITE or OUT_RK
   int zc;        // z planes per workgroup
   int wpe;       // 1 or 2 waves per SIMD
-  double* fo3;   // every face WENO: face changes of the x, y, z faces, 5 values
-                 // each (face-once corrections), or null: the per-cell kernel
+  double* fo3;   // face changes of the x, y, z faces, 5 values each (face-once
+                 // corrections: every face WENO, or the face lists), or null:
+                 // the per-cell kernel
+  unsigned int* flist;        // face lists (fused3d_flist_entries of them), or null
+  unsigned int* counts_f;     // faces each workgroup listed, per direction
+  unsigned int* offs_f;       // their exclusive prefix sums (one more entry)
   int n[3];
   KGrid g;
   KPhys ph;
@@ -48,6 +52,12 @@ size_t fused3d_face_doubles(const int n[3]);
 // any z chunk (one workgroup per column tile and plane at most).
 inline size_t fused3d_count_entries(const int n[3]) {
   return (size_t)((n[0] + FT_X - 1) / FT_X) * ((n[1] + FT_Y - 1) / FT_Y) * n[2];
+}
+// Entries of the face lists (FusedLaunch::flist): the faces of the three
+// directions, each direction's faces once.
+inline size_t fused3d_flist_entries(const int n[3]) {
+  const size_t nx = n[0], ny = n[1], nz = n[2];
+  return (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1);
 }
 
 }  // namespace wl2

@@ -1128,3 +1128,46 @@ def test_reduced_config_hundred_steps(orc, capi, name):
     assert stg == 0 and k == 100
     assert abs(t_g - t_o) <= 1e-12 * t_o
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("shape,zc,variant", [
+    ((64, 64, 64), 0, "default"), ((37, 33, 29), 7, "default"), ((37, 33, 29), 0, "per_face"),
+    ((20, 18, 17), 3, "roe"), ((40, 31, 22), 0, "hybrid_b01"), ((17, 16, 5), 2, "default")])
+def test_3d_face_lists_bitwise(capi, shape, zc, variant):
+    """3D hybrid corrections from the face lists (each listed face's change
+    once, then per listed cell the sum of its faces) give the same bits as
+    the per-cell corrections (every flagged face computed for both of its
+    cells), for edge tiles, several z chunks and scheme variants: the
+    right-hand side and eight device-clock steps."""
+    import torch
+    nx, ny, nz = shape
+    say(f"[face lists] shape={shape} zc={zc} variant={variant}")
+    U, dx = _turb_jump(nx, ny, nz, 9)
+    p = capi.params_default(*shape, dx, bc=[0] * 6, **VARIANTS[variant])
+    outs, rhss, clocks = [], [], []
+    for path in (capi.PATH_FUSED, capi.PATH_FUSED_CELLS):
+        ctx = capi.Context(*shape, dx, G, p)
+        ctx.tune(path, zc, 0)
+        Ud = to_dev(U)
+        r = torch.full_like(Ud, float("nan"))
+        ctx.rhs(Ud, r)
+        ctx.advance(Ud, 8, 1e300)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        if path == capi.PATH_FUSED:
+            nf = 0
+            for d in range(3):
+                n = U.shape[0] * (nx * ny * nz // shape[d]) * (shape[d] + 1)
+                fl = torch.zeros(n, dtype=torch.uint8, device="cuda")
+                sg = torch.zeros(n, dtype=torch.float64, device="cuda")
+                ctx.face_debug(Ud, d, fl, sg)
+                nf += int((fl == 0).sum().item())
+            say(f"    WENO face-fields after 8 steps: {nf}")
+            assert nf > 0
+        outs.append(to_host(Ud))
+        rhss.append(to_host(r))
+        clocks.append(ctx.clock())
+        ctx.close()
+    assert np.array_equal(rhss[0], rhss[1])
+    assert clocks[0] == clocks[1]
+    assert np.array_equal(outs[0], outs[1])
