@@ -74,7 +74,9 @@ struct FusedArgs {
   unsigned int* flist;
   unsigned int* counts_f;    // faces each workgroup listed, [direction][region]
   unsigned int* offs_f;      // their exclusive prefix sums over (direction, region)
-  double* D;                 // face changes: x, y, z faces, 5 values each, [v][face]
+  double* D;                 // face changes of the listed faces: x, y, z faces, 5
+                             // values each, [face][v] (a face's values together:
+                             // the lists visit faces in no spatial order)
 };
 
 // The correction list is cut into one region per workgroup of the stage
@@ -684,7 +686,7 @@ __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g
 // Face lists, face-once corrections: every entry of the three face lists
 // (taken as one index space over (direction, region), the offsets in LDS or
 // written by list_scan_kernel) gives one face, whose change of flux (WENO
-// minus linear, Eq.(20)-(28), (33)) goes to D[v][face] of its direction.
+// minus linear, Eq.(20)-(28), (33)) goes to D[face][v] of its direction.
 // One face per lane, and the lanes of a wavefront take consecutive entries,
 // so that a wavefront runs faces of one direction (except where the x list
 // meets the y list and the y list the z list).  The change depends on the
@@ -704,7 +706,7 @@ __global__ __launch_bounds__(128, 2) void weno_flist3d_kernel(FusedArgs a, KGrid
   }
   const unsigned int n = offs[nseg];
   const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
+  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz;
   const unsigned int threads = gridDim.x * blockDim.x;
   for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += threads) {
     const int seg = find_segment(offs, nseg, i);
@@ -722,27 +724,23 @@ __global__ __launch_bounds__(128, 2) void weno_flist3d_kernel(FusedArgs a, KGrid
     const long long f = x + ex * (y + ey * (long long)z);
     double dF[NV];
     double* D;
-    long long nf;
     if (d == 0) {
       face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, z, 0, dF);
       D = a.D;
-      nf = nfx;
     } else if (d == 1) {
       face_delta<NV, 1, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, z, 0, dF);
-      D = a.D + 5 * nfx;
-      nf = nfy;
+      D = a.D + NV * nfx;
     } else {
       face_delta<NV, 2, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[2], x, y, z, 0, dF);
-      D = a.D + 5 * (nfx + nfy);
-      nf = nfz;
+      D = a.D + NV * (nfx + nfy);
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) D[v * nf + (long long)f] = dF[v];
+    for (int v = 0; v < NV; ++v) D[NV * f + v] = dF[v];
   }
 }
 
 // Face lists, per listed cell: the changes of its flagged faces read from D
-// and summed in the fixed order x-, x+, y-, y+, z-, z+ (+ below, - above),
+// ([face][v]) and summed in the fixed order x-, x+, y-, y+, z-, z+ (+ below, - above),
 // then added to the output exactly as weno_fix3d_kernel adds them (the same
 // bits); with a.cfl set the CFL speed of the corrected cell is folded; the
 // next stage's list counter is cleared.
@@ -766,9 +764,8 @@ __global__ __launch_bounds__(256) void weno_sumlist3d_kernel(FusedArgs a, KGrid 
   }
   const unsigned int n = offs[nreg];
   const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
-  const double* Dd[3] = {a.D, a.D + 5 * nfx, a.D + 5 * (nfx + nfy)};
-  const long long nf[3] = {nfx, nfy, nfz};
+  const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz;
+  const double* Dd[3] = {a.D, a.D + NV * nfx, a.D + NV * (nfx + nfy)};
   double cfl_max = 0.0;
   bool cfl_bad = false;
   const unsigned int threads = gridDim.x * blockDim.x;
@@ -791,7 +788,7 @@ __global__ __launch_bounds__(256) void weno_sumlist3d_kernel(FusedArgs a, KGrid 
       const long long idx = lof[dir] + ((f & 1) ? step[dir] : 0);
       const double sg = (f & 1) ? -1.0 : 1.0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += sg * Dd[dir][v * nf[dir] + idx];
+      for (int v = 0; v < NV; ++v) acc[v] += sg * Dd[dir][NV * idx + v];
     }
     double un[NV];
 #pragma unroll
