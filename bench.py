@@ -190,8 +190,21 @@ def other_configs(torch, capi, workloads):
                   {"cfl": 0.2, "bc": [0, 0, 1, 1, 1, 1]}))
     U, dx, _ = workloads.four_quadrant_2d(1024, 1024, 2024)
     cases.append(("quad2d_1024x1024_200steps", U, dx, (1024, 1024, 1), 1e300, 200, {}))
+    # the Mach 2000 jet (Sec. 4.7, 640 x 160 to t = 0.001, global LF as the
+    # paper's 2D runs): the WENO-IS weights of Eq.(14)-(15), and the present
+    # scheme with lambda = 3600 sigma^s (with the printed c = 1 it goes
+    # non-physical at step 52)
+    Uj, dxj, infj = workloads.mach2000_jet(640, 160)
+    jet = {"bc": [3, 1, 2, 1, 1, 1], "cfl": 0.25, "split": 1}
+    cases.append(("jet640x160_t0.001_weno_is_b01", Uj, dxj, (640, 160, 1), 1e-3, None,
+                  dict(jet, hybrid=2, weights=2)))
+    cases.append(("jet640x160_t0.001_present_c3600", Uj, dxj, (640, 160, 1), 1e-3, None,
+                  dict(jet, c_reg=3600.0)))
     for name, U0, dx, shape, t_end, nsteps, kw in cases:
-        ctx = capi.Context(*shape, dx, GAMMA, capi.params_default(*shape, dx, **kw))
+        gamma = workloads.JET_GAMMA if name.startswith("jet") else GAMMA
+        ctx = capi.Context(*shape, dx, gamma, capi.params_default(*shape, dx, **kw))
+        if name.startswith("jet"):
+            ctx.set_inflow(torch.from_numpy(infj).cuda())
         ncell = shape[0] * shape[1] * shape[2]
         res = None
         for rep in range(2):  # warm-up run, then the timed one
@@ -205,7 +218,7 @@ def other_configs(torch, capi, workloads):
             else:
                 while True:
                     ctx.advance(Ud, 256, t_end)
-                    if not ctx.time()[0] < t_end:
+                    if not ctx.time()[0] < t_end or ctx.status() != 0:
                         break
             e1.record(ctx.stream)
             e1.synchronize()
@@ -225,20 +238,38 @@ def other_configs(torch, capi, workloads):
 def weighting_ratios(torch, capi, workloads, steps=200):
     """Relative cost of the schemes the paper compares (Sec. 4.5-4.6, Tables
     1-2 time the whole runs on a CPU), here as GPU time per step of the 2D
-    four-quadrant 1024^2 problem with the paper's 2D splitting (global
-    Lax-Friedrichs): the present hybrid scheme (regularized weights, Eq.(28),
-    with the switch of Eq.(33)-(35)), the WENO-IS scheme of Wang et al.
-    (pure WENO with the weights of Eq.(14)-(15)), the original WENO-IS
-    weights (Eq.(8)), pure regularized WENO (switch off) and the optimal
-    linear scheme alone (every face on the linear branch)."""
+    four-quadrant 1024^2 problem, with the paper's 2D splitting (global
+    Lax-Friedrichs) and with the local one: the present hybrid scheme
+    (regularized weights, Eq.(28), with the switch of Eq.(33)-(35)), the
+    WENO-IS scheme of Wang et al. (pure WENO with the weights of
+    Eq.(14)-(15)), the original WENO-IS weights (Eq.(8)), pure regularized
+    WENO (switch off) and the optimal linear scheme alone (every face on the
+    linear branch; it goes non-physical at the shocks of this problem, and a
+    run that stops is not timed)."""
     U0, dx, _ = workloads.four_quadrant_2d(1024, 1024, 2024)
     shape = (1024, 1024, 1)
     schemes = {"present": {}, "weno_is_b01": {"hybrid": 2, "weights": 2},
                "weno_is": {"hybrid": 2, "weights": 1}, "weno_l2is_no_switch": {"hybrid": 2},
                "linear_only": {"hybrid": 3}}
     out = {}
+    for split_name, split in (("lf", 1), ("llf", 0)):
+        res = _weighting_times(torch, capi, U0, dx, shape, schemes, split, steps)
+        base = res["present"]["ms_per_step"]
+        res["present_over"] = {k: (round(base / v["ms_per_step"], 3) if v["status"] == 0 else None)
+                               for k, v in res.items() if k != "present"}
+        out[split_name] = res
+        log(f"[bench]   weighting ratios ({split_name}): {res['present_over']}")
+    out["config"] = f"2D four-quadrant 1024^2, {steps} steps, seed 2024; lf = global LF splitting (the paper's 2D choice), llf = local LF"
+    out["paper_context"] = ("CPU wall time ratios, unnamed hardware: Present / WENO-Z = 0.728 (DMR "
+                            "512x128) and 0.772 (viscous shock tube); Present / WENO-JS = 0.840, "
+                            "0.795; Present / WENO-HY = 1.262, 1.142")
+    return out
+
+
+def _weighting_times(torch, capi, U0, dx, shape, schemes, split, steps):
+    out = {}
     for name, kw in schemes.items():
-        ctx = capi.Context(*shape, dx, GAMMA, capi.params_default(*shape, dx, split=1, **kw))
+        ctx = capi.Context(*shape, dx, GAMMA, capi.params_default(*shape, dx, split=split, **kw))
         ms = None
         for rep in range(2):  # warm-up run, then the timed one
             Ud = torch.from_numpy(U0).cuda()
@@ -249,17 +280,10 @@ def weighting_ratios(torch, capi, workloads, steps=200):
             e1.record(ctx.stream)
             e1.synchronize()
             ms = e0.elapsed_time(e1)
-        out[name] = {"ms_per_step": round(ms / steps, 5), "status": ctx.status()}
+        st = ctx.status()
+        out[name] = {"ms_per_step": round(ms / steps, 5) if st == 0 else None, "status": st}
         ctx.close()
         del Ud
-    base = out["present"]["ms_per_step"]
-    out["present_over"] = {k: round(base / v["ms_per_step"], 3) for k, v in out.items()
-                           if k != "present"}
-    out["config"] = f"2D four-quadrant 1024^2, {steps} steps, global LF splitting, seed 2024"
-    out["paper_context"] = ("CPU wall time ratios, unnamed hardware: Present / WENO-Z = 0.728 (DMR "
-                            "512x128) and 0.772 (viscous shock tube); Present / WENO-JS = 0.840, "
-                            "0.795; Present / WENO-HY = 1.262, 1.142")
-    log(f"[bench]   weighting ratios: {out['present_over']}")
     return out
 
 
