@@ -48,7 +48,8 @@ enum {
                              inflow misplaced or its state not set          */
   WL2_E_HIP = -5,         /* a HIP runtime call failed                       */
   WL2_E_NOMEM = -6,       /* device allocation failed                        */
-  WL2_E_BUDGET = -7,      /* batch: HBM budget or slot table exhausted      */
+  WL2_E_BUDGET = -7,      /* batch: HBM budget or slot table exhausted;
+                             rhs_noalloc: grid beyond its static scratch     */
   WL2_E_SLOT = -8,        /* batch: slot not in use / not finished           */
   WL2_S_NONPHYSICAL = 1   /* rho <= 0, p <= 0 or non-finite state detected   */
 };
@@ -133,6 +134,26 @@ int weno_l2is_rhs(const double *U, int nx, int ny, int nz, double dx,
  * (the cache itself is guarded by a lock).  Returns the number of contexts
  * released (>= 0), or WL2_E_HIP if a device could not be selected. */
 int weno_l2is_rhs_release(void);
+
+/* Bytes of the static device scratch of weno_l2is_rhs_noalloc (per GPU). */
+#define WL2_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* weno_l2is_rhs without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid it).  The same dU/dt, bit for bit, enqueued on hip_stream
+ * (hipStream_t; NULL = the null stream).  Its scratch (control block and
+ * correction list: 8 bytes per cell plus 4.6 KB, and 8 bytes per column
+ * tile and plane in 3D) lives in a static device array of
+ * WL2_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, held until the
+ * process ends; grids whose scratch does not fit (about 8.3M cells) are
+ * refused with WL2_E_BUDGET before any device work.  Every call on a GPU
+ * shares that GPU's array (the control block is cleared by a kernel at the
+ * start of each call): calls that overlap on one GPU (different streams,
+ * different threads) race, so the caller orders them.  No inflow side
+ * (WL2_E_BC).  Other arguments and errors as weno_l2is_rhs. */
+int weno_l2is_rhs_noalloc(const double *U, int nx, int ny, int nz, double dx,
+                          double gamma, const weno_l2is_params *params,
+                          double *dUdt, void *hip_stream);
 
 /* The same on a context (its stream and scratch); the same overlap rule. */
 int weno_l2is_rhs_ctx(weno_l2is_ctx *ctx, const double *U, double *dUdt);

@@ -61,6 +61,7 @@ def lib():
         "weno_l2is_rhs": (ip, [vp, ip, ip, ip, dp, dp, pp, vp]),
         "weno_l2is_rhs_ctx": (ip, [vp, vp, vp]),
         "weno_l2is_rhs_release": (ip, []),
+        "weno_l2is_rhs_noalloc": (ip, [vp, ip, ip, ip, dp, dp, pp, vp, vp]),
         "weno_l2is_step": (ip, [vp, vp, dp]),
         "weno_l2is_advance": (ip, [vp, vp, ip, dp]),
         "weno_l2is_set_time": (ip, [vp, dp]),
@@ -136,6 +137,16 @@ def rhs(U: torch.Tensor, nx: int, ny: int, nz: int, dx: float, gamma: float, par
     _, nvar, ncell = grid_dims(nx, ny, nz)
     _chk(lib().weno_l2is_rhs(_ptr(U, nvar * ncell), nx, ny, nz, dx, gamma, C.byref(params),
                              _ptr(dUdt, nvar * ncell)), "rhs")
+
+
+def rhs_noalloc(U: torch.Tensor, nx: int, ny: int, nz: int, dx: float, gamma: float,
+                params: Params, dUdt: torch.Tensor, stream=None) -> None:
+    """weno_l2is_rhs without device allocation (static scratch), on `stream`
+    (a torch stream; None: the current one)."""
+    _, nvar, ncell = grid_dims(nx, ny, nz)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _chk(lib().weno_l2is_rhs_noalloc(_ptr(U, nvar * ncell), nx, ny, nz, dx, gamma, C.byref(params),
+                                     _ptr(dUdt, nvar * ncell), C.c_void_p(s.cuda_stream)), "rhs_noalloc")
 
 
 def rhs_release() -> int:

@@ -386,6 +386,51 @@ std::map<std::tuple<int, int, int, int>, weno_l2is_ctx*> g_cache;
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free rhs
+// Static scratch of weno_l2is_rhs_noalloc: one array per GPU, in the code
+// object.  Host code never uses the name as an address: the device address
+// of each GPU's copy comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char wl2_noalloc_scratch[WL2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch (null on failure).
+void* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(wl2_noalloc_scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_noalloc_ptr[dev] = p;
+  }
+  return g_noalloc_ptr[dev];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Scratch of one right-hand side with per-cell corrections: control block,
+// (3D) the per-workgroup list counts and their offsets, the correction list.
+size_t noalloc_bytes(const int n[3], int dim) {
+  const size_t ncell = (size_t)n[0] * n[1] * n[2];
+  size_t b = align256(sizeof(StepCtl));
+  if (dim == 3) b += align256(sizeof(unsigned int) * (2 * fused3d_count_entries(n) + 1));
+  return b + sizeof(unsigned long long) * ncell;
+}
+
+__global__ void zero_words_kernel(unsigned long long* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+}  // namespace
+
 extern "C" {
 
 int weno_l2is_params_default(weno_l2is_params* p, int nx, int ny, int nz, double dx) {
@@ -568,6 +613,60 @@ int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gam
     fill_desc(c);
   }
   return hip_err(rhs_into(c, U, dUdt));
+}
+
+int weno_l2is_rhs_noalloc(const double* U, int nx, int ny, int nz, double dx, double gamma,
+                          const weno_l2is_params* params, double* dUdt, void* hip_stream) {
+  if (!U || !dUdt) return WL2_E_NULL;
+  int rc = validate(nx, ny, nz, dx, gamma, params);
+  if (rc) return rc;
+  if (params->bc[0] == WL2_BC_INFLOW) return WL2_E_BC;  // no context to hold its state
+  const int dim = nz > 1 ? 3 : (ny > 1 ? 2 : 1);
+  const size_t nc = (size_t)nx * ny * nz;
+  if (overlaps(U, dUdt, (size_t)(2 + dim) * nc)) return WL2_E_PARAM;
+  const int n[3] = {nx, ny, nz};
+  if (noalloc_bytes(n, dim) > (size_t)WL2_NOALLOC_SCRATCH_BYTES) return WL2_E_BUDGET;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WL2_E_HIP;
+  unsigned char* base = (unsigned char*)noalloc_scratch(dev);
+  if (!base) return WL2_E_HIP;
+  // a context on the host stack over the scratch: nothing is allocated;
+  // the per-cell correction kernels need only the list (no face buffers)
+  weno_l2is_ctx c;
+  c.n[0] = nx;
+  c.n[1] = ny;
+  c.n[2] = nz;
+  c.dim = dim;
+  c.nvar = dim + 2;
+  c.ncell = (long long)nc;
+  c.dx = dx;
+  c.gamma = gamma;
+  c.p = *params;
+  c.stream = (hipStream_t)hip_stream;
+  c.device = dev;
+  c.U1 = c.U2 = c.acc = nullptr;
+  size_t off = 0;
+  c.ctl = (StepCtl*)(base + off);
+  off += align256(sizeof(StepCtl));
+  if (dim == 3) {
+    c.counts = (unsigned int*)(base + off);
+    off += align256(sizeof(unsigned int) * (2 * fused3d_count_entries(n) + 1));
+  }
+  c.list = (unsigned long long*)(base + off);
+  c.path = WL2_PATH_FUSED_CELLS;
+  c.zchunk = 0;
+  c.wpe = 2;
+  c.list_par = 0;
+  c.list_dirty = true;  // both list counters cleared by the first launch
+  c.timing = false;
+  fill_desc(&c);
+  // the control block starts at zero (a kernel, not a memset: the call may
+  // be captured into a graph)
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, c.stream,
+                     (unsigned long long*)c.ctl, sizeof(StepCtl) / sizeof(unsigned long long));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = rhs_into(&c, U, dUdt);
+  return hip_err(e);
 }
 
 int weno_l2is_rhs_release(void) {

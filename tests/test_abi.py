@@ -103,3 +103,12 @@ def test_arguments_refused_before_any_device_call():
         assert lib.weno_l2is_strerror(code)
     # no rhs call has cached a context: releasing touches no device
     assert lib.weno_l2is_rhs_release() == 0
+    # the allocation-free rhs refuses, before any device call, grids beyond
+    # its static scratch, inflow sides and the refusals of weno_l2is_rhs
+    lib.weno_l2is_rhs_noalloc.argtypes = lib.weno_l2is_rhs.argtypes + [vp]
+    big = params(4096, 4096, 1)
+    assert lib.weno_l2is_rhs_noalloc(fake, 4096, 4096, 1, 0.1, 1.4, ctypes.byref(big), vp((1 << 41)), None) == capi.E_BUDGET
+    inflow = params(8, 1, 1, bc=[3, 1, 1, 1, 1, 1])
+    assert lib.weno_l2is_rhs_noalloc(fake, 8, 1, 1, 0.1, 1.4, ctypes.byref(inflow), vp((1 << 41)), None) == capi.E_BC
+    assert lib.weno_l2is_rhs_noalloc(None, 8, 1, 1, 0.1, 1.4, ctypes.byref(p), fake, None) == capi.E_NULL
+    assert lib.weno_l2is_rhs_noalloc(fake, 8, 1, 1, 0.1, 1.4, ctypes.byref(p), fake, None) == capi.E_PARAM
