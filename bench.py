@@ -173,9 +173,11 @@ def other_configs(torch, capi, workloads):
     Shu-Osher 1600 to t = 1.8 (transmissive), the interacting blast waves on
     400 cells to t = 0.038 (reflective walls, Roe splitting), the
     broadband sound packet on 128 cells for one period (periodic, CFL 0.2),
-    2D four-quadrant 1024^2 for 200 steps.  Each through weno_l2is_advance on
-    the fused 1D/2D kernel, timed with events on the library's stream after
-    one untimed warm-up run."""
+    2D four-quadrant 1024^2 for 200 steps, the Mach 2000 jet on 640 x 160 to
+    t = 0.001, the double Mach reflection on 512 x 128 and 1024 x 256 to
+    t = 0.2.  Each through weno_l2is_advance on the fused 1D/2D kernel,
+    timed with events on the library's stream after one untimed warm-up
+    run."""
     out = {}
     cases = []
     U, dx = workloads.sod(200)
@@ -200,11 +202,21 @@ def other_configs(torch, capi, workloads):
                   dict(jet, hybrid=2, weights=2)))
     cases.append(("jet640x160_t0.001_present_c3600", Uj, dxj, (640, 160, 1), 1e-3, None,
                   dict(jet, c_reg=3600.0)))
+    # the double Mach reflection (Sec. 4.5) to t = 0.2 on the paper's two
+    # grids (Table 1 times the 512 x 128 run)
+    infs = {}
+    for dnx, dny in ((512, 128), (1024, 256)):
+        Ud, dxd, prm, infd = workloads.double_mach(dnx, dny)
+        name = f"dmr{dnx}x{dny}_t0.2"
+        infs[name] = infd
+        cases.append((name, Ud, dxd, (dnx, dny, 1), 0.2, None, prm))
     for name, U0, dx, shape, t_end, nsteps, kw in cases:
         gamma = workloads.JET_GAMMA if name.startswith("jet") else GAMMA
         ctx = capi.Context(*shape, dx, gamma, capi.params_default(*shape, dx, **kw))
         if name.startswith("jet"):
             ctx.set_inflow(torch.from_numpy(infj).cuda())
+        if name in infs:
+            ctx.set_inflow(torch.from_numpy(infs[name]).cuda())
         ncell = shape[0] * shape[1] * shape[2]
         res = None
         for rep in range(2):  # warm-up run, then the timed one

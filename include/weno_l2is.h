@@ -60,9 +60,18 @@ enum {
  * mirrors the interior with the normal momentum negated (Sec. 4.3, 4.7);
  * INFLOW gives the ghosts a prescribed state per x line, set with
  * weno_l2is_set_inflow (the left side of the jet of Sec. 4.7; allowed on the
- * x- side of a 1D or 2D grid held by a context only). */
+ * x- side of a 1D or 2D grid held by a context only).  The state sides of
+ * the double Mach reflection (Sec. 4.5), on the y sides of 2D grids (not in
+ * the batch engine): STATE_WALL gives the ghosts under the cells centred
+ * left of x = bgeom[0] the state bstate[0] and mirrors the interior (as
+ * REFLECTIVE) elsewhere; STATE_FRONT gives a ghost centred at (x, y) the
+ * state bstate[0] if x < bgeom[1] + bgeom[2] y + bgeom[3] t, else bstate[1]
+ * (a straight front moving along x; t = the stage's time on the context's
+ * clock: t, t + dt, t + dt/2 within a step of weno_l2is_advance, the
+ * clock's t for a right-hand side; the stateless calls use t = 0).  Cell
+ * centres lie at ((i + 1/2) dx, (j + 1/2) dx). */
 enum { WL2_BC_PERIODIC = 0, WL2_BC_TRANSMISSIVE = 1, WL2_BC_REFLECTIVE = 2,
-       WL2_BC_INFLOW = 3 };
+       WL2_BC_INFLOW = 3, WL2_BC_STATE_WALL = 4, WL2_BC_STATE_FRONT = 5 };
 
 /* Flux-splitting speed alpha^s of Eq.(21): LLF = max over the six stencil
  * cells of |lambda^s(U_m)| (the hot path); LF = max over the whole grid per
@@ -95,6 +104,9 @@ typedef struct weno_l2is_params {
   int bc[6];        /* x-, x+, y-, y+, z-, z+ : WL2_BC_*; periodic is paired  */
   double thr_L[3];  /* L of Eq.(35) per direction; default n_d * dx           */
   int weights;      /* WL2_W_*: weights of the WENO branch; default L2IS      */
+  double bstate[2][5];  /* conserved states of STATE_WALL / STATE_FRONT ghosts
+                           (first nvar values); default 0                   */
+  double bgeom[4];  /* wall start x; front x0, dx/dy, dx/dt; default 0        */
 } weno_l2is_params;
 
 typedef struct weno_l2is_ctx weno_l2is_ctx;
@@ -149,8 +161,8 @@ int weno_l2is_rhs_release(void);
  * refused with WL2_E_BUDGET before any device work.  Every call on a GPU
  * shares that GPU's array (the control block is cleared by a kernel at the
  * start of each call): calls that overlap on one GPU (different streams,
- * different threads) race, so the caller orders them.  No inflow side
- * (WL2_E_BC).  Other arguments and errors as weno_l2is_rhs. */
+ * different threads) race, so the caller orders them.  No inflow or state
+ * side (WL2_E_BC).  Other arguments and errors as weno_l2is_rhs. */
 int weno_l2is_rhs_noalloc(const double *U, int nx, int ny, int nz, double dx,
                           double gamma, const weno_l2is_params *params,
                           double *dUdt, void *hip_stream);

@@ -24,7 +24,15 @@ extern "C" {
 #endif
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_TRANSMISSIVE = 1, ORC_BC_REFLECTIVE = 2,
-       ORC_BC_INFLOW = 3 /* x- side of a 1D/2D grid: ghosts = inflow[] */ };
+       ORC_BC_INFLOW = 3,      /* x- side of a 1D/2D grid: ghosts = inflow[]  */
+       ORC_BC_STATE_WALL = 4,  /* y side of a 2D grid: ghosts of the cells with
+                                  centre x < bgeom[0] hold bstate[0], the
+                                  others mirror the interior (a wall)          */
+       ORC_BC_STATE_FRONT = 5  /* y side of a 2D grid: a ghost centred at
+                                  (x, y) holds bstate[0] if x < bgeom[1] +
+                                  bgeom[2] y + bgeom[3] time, else bstate[1]
+                                  (a straight front moving along x)           */
+};
 enum { ORC_SPLIT_LLF = 0, ORC_SPLIT_LF = 1, ORC_SPLIT_ROE = 2 };
 enum {
   ORC_HYB_PER_FIELD = 0,  /* linear flux for field s iff sigma^s < eps      */
@@ -54,10 +62,16 @@ typedef struct {
                            ghosts left of x line y, inflow[v*ny + y]; else
                            unused (Sec. 4.7, the jet's left boundary)      */
   int weights;      /* ORC_W_*: weights of the nonlinear reconstruction       */
+  double bstate[2][5];  /* conserved states of the STATE_WALL / STATE_FRONT
+                           ghosts (first nvar values of each)                 */
+  double bgeom[4];  /* x of the wall's start; x0, dx/dy, dx/dt of the front   */
+  double time;      /* time of the state (stage time inside orc_step; the
+                       start time of orc_run); read by STATE_FRONT            */
 } orc_params;
 
 /* Fill defaults for a grid: thr_L[d] = n_d * dx, transmissive boundaries,
- * inflow = NULL, weights ORC_W_L2IS. */
+ * inflow = NULL, weights ORC_W_L2IS, boundary states and geometry zero,
+ * time 0.  Cell centres lie at ((i + 1/2) dx, (j + 1/2) dx, ...). */
 int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx);
 
 /* Scalar WENO-L2IS reconstruction at x_{j+1/2} from a[0..4] = f_{j-2..j+2}
@@ -117,9 +131,11 @@ int orc_face_debug(const double *U, int nx, int ny, int nz, double dx,
 int orc_cfl_dt(const double *U, int nx, int ny, int nz, double dx,
                double gamma, double cfl, double *dt);
 
-/* One third-order SSP Runge-Kutta step in place.  dt_in > 0: use it;
- * otherwise the CFL dt of the current state, whose maximum speed also takes
- * the inflow ghost states of an ORC_BC_INFLOW side.  dt_used may be NULL. */
+/* One third-order SSP Runge-Kutta step in place from time p->time.  dt_in >
+ * 0: use it; otherwise the CFL dt of the current state, whose maximum speed
+ * also takes the inflow ghost states of an ORC_BC_INFLOW side.  The stages
+ * evaluate the right-hand side at times t, t + dt, t + dt/2 (the times of
+ * the Shu-Osher stages).  dt_used may be NULL. */
 int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
              const orc_params *p, double dt_in, double *dt_used);
 
@@ -128,7 +144,8 @@ int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
  * on it. */
 int orc_threads(int n);
 
-/* Advance to t_end (last step clipped) or max_steps, whichever first.
+/* Advance from p->time to t_end (last step clipped) or max_steps, whichever
+ * first.
  * Returns the status of the last check. */
 int orc_run(double *U, int nx, int ny, int nz, double dx, double gamma,
             const orc_params *p, double t_end, int max_steps, double *t_out,

@@ -24,6 +24,7 @@ LIB_PATH = os.environ.get("ORACLE_L2IS_LIB") or DEFAULT_LIB  # what lib() loads
 SOURCES = ["weno_scalar.c", "charsys.c", "face.c", "solver.c"]
 
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
+BC_STATE_WALL, BC_STATE_FRONT = 4, 5
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
 W_L2IS, W_IS, W_IS_B01 = 0, 1, 2
@@ -55,6 +56,9 @@ class Params(C.Structure):
         ("thr_L", C.c_double * 3),
         ("inflow", C.POINTER(C.c_double)),
         ("weights", C.c_int),
+        ("bstate", (C.c_double * 5) * 2),
+        ("bgeom", C.c_double * 4),
+        ("time", C.c_double),
     ]
 
 
@@ -117,6 +121,13 @@ def params(nx: int, ny: int, nz: int, dx: float, **kw) -> Params:
         if k == "bc":
             for i, b in enumerate(v):
                 p.bc[i] = int(b)
+        elif k == "bstate":
+            for s_, st in enumerate(v):
+                for i, x in enumerate(st):
+                    p.bstate[s_][i] = float(x)
+        elif k == "bgeom":
+            for i, b in enumerate(v):
+                p.bgeom[i] = float(b)
         elif k == "thr_L":
             for i, b in enumerate(v):
                 p.thr_L[i] = float(b)

@@ -24,6 +24,7 @@
 typedef struct {
   int n[3], dim, nvar;
   long long ncell;
+  double dx;  /* cell size (cell centres at (i + 1/2) dx): state ghosts */
 } grid_t;
 
 static int grid_init(grid_t *g, int nx, int ny, int nz) {
@@ -35,6 +36,7 @@ static int grid_init(grid_t *g, int nx, int ny, int nz) {
   g->dim = nz > 1 ? 3 : (ny > 1 ? 2 : 1);
   g->nvar = g->dim + 2;
   g->ncell = (long long)nx * ny * nz;
+  g->dx = 0.0;
   return 0;
 }
 
@@ -42,7 +44,10 @@ static int check_params(const grid_t *g, const orc_params *p) {
   int d;
   for (d = 0; d < g->dim; ++d) {
     int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < 0 || lo > 3 || hi < 0 || hi > 2) return -1;
+    int slo = lo == ORC_BC_STATE_WALL || lo == ORC_BC_STATE_FRONT;
+    int shi = hi == ORC_BC_STATE_WALL || hi == ORC_BC_STATE_FRONT;
+    if (lo < 0 || lo > 5 || hi < 0 || hi > 5 || hi == ORC_BC_INFLOW) return -1;
+    if ((slo || shi) && (d != 1 || g->dim != 2)) return -1;
     if (lo == ORC_BC_INFLOW && (d != 0 || g->dim == 3 || !p->inflow)) return -1;
     if ((lo == ORC_BC_PERIODIC) != (hi == ORC_BC_PERIODIC)) return -1;
     if ((lo == ORC_BC_REFLECTIVE || hi == ORC_BC_REFLECTIVE) && g->n[d] < 3) return -1;
@@ -65,6 +70,9 @@ int orc_params_default(orc_params *p, int nx, int ny, int nz, double dx) {
   for (d = 0; d < 6; ++d) p->bc[d] = ORC_BC_TRANSMISSIVE;
   p->inflow = 0;
   p->weights = ORC_W_L2IS;
+  memset(p->bstate, 0, sizeof(p->bstate));
+  memset(p->bgeom, 0, sizeof(p->bgeom));
+  p->time = 0.0;
   p->thr_L[0] = nx * dx;
   p->thr_L[1] = ny * dx;
   p->thr_L[2] = nz * dx;
@@ -105,9 +113,29 @@ static int ghost_map(int k, int n, int bclo, int bchi, int *flip) {
  * along d is k (a ghost when outside 0..n-1), boundary rules applied. */
 static double cell_value(const grid_t *g, const orc_params *p, const double *U,
                          int d, int v, int k, const int idx[3]) {
-  int flip, src = ghost_map(k, g->n[d], p->bc[2 * d], p->bc[2 * d + 1], &flip);
+  int flip, src;
   int i[3];
   double val;
+  if (k < 0 || k >= g->n[d]) {
+    /* state ghosts of a y side (2D): a prescribed state where the rule
+     * gives one, else the mirror image of the interior */
+    int kind = p->bc[2 * d + (k < 0 ? 0 : 1)];
+    if (kind == ORC_BC_STATE_WALL || kind == ORC_BC_STATE_FRONT) {
+      double xc = (idx[0] + 0.5) * g->dx, yc = (k + 0.5) * g->dx;
+      if (kind == ORC_BC_STATE_FRONT)
+        return xc < p->bgeom[1] + p->bgeom[2] * yc + p->bgeom[3] * p->time ? p->bstate[0][v]
+                                                                          : p->bstate[1][v];
+      if (xc < p->bgeom[0]) return p->bstate[0][v];
+      src = k < 0 ? -1 - k : 2 * g->n[d] - 1 - k;
+      i[0] = idx[0];
+      i[1] = idx[1];
+      i[2] = idx[2];
+      i[d] = src;
+      val = U[at(g, v, i[0], i[1], i[2])];
+      return v == 1 + d ? -val : val;
+    }
+  }
+  src = ghost_map(k, g->n[d], p->bc[2 * d], p->bc[2 * d + 1], &flip);
   if (src < 0) /* inflow ghost: the state given for this x line */
     return p->inflow[(long long)v * g->n[1] * g->n[2] + idx[1] + (long long)g->n[1] * idx[2]];
   i[0] = idx[0];
@@ -228,6 +256,7 @@ int orc_rhs(const double *U, int nx, int ny, int nz, double dx, double gamma,
   long long k;
   if (!U || !dUdt || !p || !(dx > 0.0) || !(gamma > 1.0)) return -1;
   if (grid_init(&g, nx, ny, nz) || check_params(&g, p)) return -1;
+  g.dx = dx;
   for (k = 0; k < g.ncell * g.nvar; ++k) dUdt[k] = 0.0;
   for (d = 0; d < g.dim; ++d) {
     rc = add_direction(&g, p, gamma, dx, d, U, dUdt);
@@ -245,6 +274,7 @@ int orc_rhs_at(const double *U, int nx, int ny, int nz, double dx,
   if (!U || !out || !p || !cell || ncells < 0 || !(dx > 0.0) || !(gamma > 1.0))
     return -1;
   if (grid_init(&g, nx, ny, nz) || check_params(&g, p)) return -1;
+  g.dx = dx;
   if (p->split == ORC_SPLIT_LF)
     for (d = 0; d < g.dim; ++d) lf_speeds(&g, U, gamma, d, alpha_lf[d]);
   for (q = 0; q < ncells; ++q) {
@@ -286,6 +316,7 @@ int orc_face_debug(const double *U, int nx, int ny, int nz, double dx,
   int fn[3];
   if (!U || !flags || !sigma || !p || !(dx > 0.0) || !(gamma > 1.0)) return -1;
   if (grid_init(&g, nx, ny, nz) || check_params(&g, p)) return -1;
+  g.dx = dx;
   if (d < 0 || d >= g.dim) return -1;
   n = g.n[d];
   nlines = g.ncell / n;
@@ -401,6 +432,7 @@ int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
   long long k, N;
   double dt, *U1, *U2, *Lk;
   int rc, st = 0;
+  orc_params ps;
   if (!U || !p || !(dx > 0.0) || !(gamma > 1.0)) return -1;
   if (grid_init(&g, nx, ny, nz) || check_params(&g, p)) return -1;
   N = g.ncell * g.nvar;
@@ -420,14 +452,17 @@ int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
     free(Lk);
     return -2;
   }
+  ps = *p; /* the stages' own times: t, t + dt, t + dt/2 */
   /* U1 = U + dt L(U) */
-  rc = orc_rhs(U, nx, ny, nz, dx, gamma, p, Lk);
+  rc = orc_rhs(U, nx, ny, nz, dx, gamma, &ps, Lk);
   for (k = 0; k < N && !rc; ++k) U1[k] = U[k] + dt * Lk[k];
   /* U2 = 3/4 U + 1/4 (U1 + dt L(U1)) */
-  if (!rc) rc = orc_rhs(U1, nx, ny, nz, dx, gamma, p, Lk);
+  ps.time = p->time + dt;
+  if (!rc) rc = orc_rhs(U1, nx, ny, nz, dx, gamma, &ps, Lk);
   for (k = 0; k < N && !rc; ++k) U2[k] = 0.75 * U[k] + 0.25 * (U1[k] + dt * Lk[k]);
   /* U = 1/3 U + 2/3 (U2 + dt L(U2)) */
-  if (!rc) rc = orc_rhs(U2, nx, ny, nz, dx, gamma, p, Lk);
+  ps.time = p->time + 0.5 * dt;
+  if (!rc) rc = orc_rhs(U2, nx, ny, nz, dx, gamma, &ps, Lk);
   for (k = 0; k < N && !rc; ++k)
     U[k] = (1.0 / 3.0) * U[k] + (2.0 / 3.0) * (U2[k] + dt * Lk[k]);
   free(U1);
@@ -440,16 +475,20 @@ int orc_step(double *U, int nx, int ny, int nz, double dx, double gamma,
 int orc_run(double *U, int nx, int ny, int nz, double dx, double gamma,
             const orc_params *p, double t_end, int max_steps, double *t_out,
             int *steps_out) {
-  double t = 0.0, dt;
+  double t, dt;
   int steps = 0, st = 0;
   grid_t g;
+  orc_params pt;
   if (!U || !p || !(dx > 0.0) || !(gamma > 1.0)) return -1;
   if (grid_init(&g, nx, ny, nz) || check_params(&g, p)) return -1;
+  pt = *p;
+  t = p->time;
   while (t < t_end && steps < max_steps) {
     st = scheme_dt(U, &g, dx, gamma, p, &dt);
     if (st) break;
     if (t + dt > t_end) dt = t_end - t;
-    st = orc_step(U, nx, ny, nz, dx, gamma, p, dt, 0);
+    pt.time = t;
+    st = orc_step(U, nx, ny, nz, dx, gamma, &pt, dt, 0);
     if (st) break;
     t += dt;
     ++steps;

@@ -18,7 +18,7 @@ LIB_PATH = _build.LIB
 
 OK, E_NULL, E_SHAPE, E_PARAM, E_BC, E_HIP, E_NOMEM, E_BUDGET, E_SLOT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 S_NONPHYSICAL = 1
-BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW, BC_STATE_WALL, BC_STATE_FRONT = 0, 1, 2, 3, 4, 5
 SPLIT_LLF, SPLIT_LF, SPLIT_ROE = 0, 1, 2
 HYB_PER_FIELD, HYB_PER_FACE, HYB_WENO_ONLY, HYB_LINEAR_ONLY = 0, 1, 2, 3
 PATH_AUTO, PATH_SWEEPS, PATH_FUSED, PATH_FUSED_CELLS = 0, 1, 2, 3
@@ -40,6 +40,8 @@ class Params(C.Structure):
         ("bc", C.c_int * 6),
         ("thr_L", C.c_double * 3),
         ("weights", C.c_int),
+        ("bstate", (C.c_double * 5) * 2),
+        ("bgeom", C.c_double * 4),
     ]
 
 
@@ -122,10 +124,14 @@ def params_default(nx: int, ny: int, nz: int, dx: float, **kw) -> Params:
     p = Params()
     _chk(lib().weno_l2is_params_default(C.byref(p), nx, ny, nz, dx), "params_default")
     for k, v in kw.items():
-        if k in ("bc", "thr_L"):
+        if k in ("bc", "thr_L", "bgeom"):
             arr = getattr(p, k)
             for i, b in enumerate(v):
                 arr[i] = b
+        elif k == "bstate":
+            for s, st in enumerate(v):
+                for i, x in enumerate(st):
+                    p.bstate[s][i] = float(x)
         else:
             setattr(p, k, v)
     return p

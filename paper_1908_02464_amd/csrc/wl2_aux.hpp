@@ -60,6 +60,7 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
   if (s_floor > smax) smax = s_floor;
   if (threadIdx.x != 0) return;
   double dt = dt_fixed > 0.0 ? dt_fixed : cfl_dx / smax;
+  ctl->t0 = ctl->t;  // the stages of the step run at t0, t0 + dt, t0 + dt/2
   if (use_clock) {
     // the clock stops at t_end and at the first non-physical state
     const double t = ctl->t, te = ctl->t_end;
@@ -72,6 +73,52 @@ __global__ __launch_bounds__(RED_BLOCK) void cfl_reduce_kernel(const double* __r
     }
   }
   ctl->dt = dt;
+}
+
+// State ghosts of the y sides of a 2D grid (Sec. 4.5: the double Mach
+// reflection), for one stage: layer k of the low side is row -1-k, of the
+// high side row ny+k.  STATE_WALL: bstate[0] under cells centred left of
+// geom[0], the mirror image of the interior (y momentum negated) elsewhere;
+// STATE_FRONT: bstate[0] left of the front x = geom[1] + geom[2] y +
+// geom[3] t, bstate[1] right of it, at the stage time t = t0 + tc dt (tc <
+// 0: the clock's t, for a right-hand side outside a step).  One thread per
+// (side, layer, column).
+struct YGhostRule {
+  double state[2][4];
+  double geom[4];
+};
+
+[[maybe_unused]] static __global__ void ghost_fill_kernel(const double* __restrict__ U, KGrid g,
+                                                          const StepCtl* ctl, double tc, double dx,
+                                                          YGhostRule rule, double* lo, double* hi) {
+  const long long nx = g.n[0], ny = g.n[1];
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= 2 * 3 * nx) return;
+  const int side = (int)(i / (3 * nx));
+  const int layer = (int)((i / nx) % 3);
+  const long long x = i % nx;
+  const int kind = side ? g.bc_hi[1] : g.bc_lo[1];
+  double* b = side ? hi : lo;
+  if (kind < BC_STATE_WALL || b == nullptr) return;
+  const double xc = ((double)x + 0.5) * dx;
+  double u[4];
+  if (kind == BC_STATE_FRONT) {
+    const double t = tc < 0.0 ? ctl->t : ctl->t0 + tc * ctl->dt;
+    const double yc = ((double)(side ? ny + layer : -1 - layer) + 0.5) * dx;
+    const int s = xc < rule.geom[1] + rule.geom[2] * yc + rule.geom[3] * t ? 0 : 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = rule.state[s][v];
+  } else if (xc < rule.geom[0]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = rule.state[0][v];
+  } else {
+    const long long row = side ? ny - 1 - layer : layer;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = U[v * g.ncell + row * nx + x];
+    u[2] = -u[2];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) b[((long long)layer * 4 + v) * nx + x] = u[v];
 }
 
 // Program the device clock target (enqueued, no host synchronisation) and

@@ -322,6 +322,7 @@ int weno_l2is_batch_admit(weno_l2is_batch* b, int nx, int ny, int nz, double dx,
   if (nz > 1) return WL2_E_SHAPE;
   if (p->split == WL2_SPLIT_LF) return WL2_E_PARAM;
   if (p->bc[0] == WL2_BC_INFLOW) return WL2_E_BC;
+  if (p->bc[2] >= WL2_BC_STATE_WALL || p->bc[3] >= WL2_BC_STATE_WALL) return WL2_E_BC;
   if (!(t_end > 0.0) || !(t_end < 1e300)) return WL2_E_PARAM;
   int s = -1;
   for (int i = 0; i < b->max_slots; ++i)

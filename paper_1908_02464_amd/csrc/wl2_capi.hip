@@ -39,6 +39,7 @@ struct weno_l2is_ctx {
   unsigned int* flist = nullptr;   // 3D hybrid: faces needing the WENO flux
   unsigned int* counts = nullptr;  // 3D: entries each stage-kernel workgroup listed
   double* inflow = nullptr;        // x- inflow side: ghost state [nvar][ny*nz]
+  double* ygh = nullptr;           // y state sides: ghost rows of both, [side][layer][nvar][nx]
   bool inflow_set = false;         // weno_l2is_set_inflow has been called
   double inflow_speed = 0.0;       // CFL speed sum_d(|u_d| + c), max over the inflow states
   StepCtl* ctl;
@@ -116,6 +117,30 @@ int validate(int nx, int ny, int nz, double dx, double gamma, const weno_l2is_pa
 void fill_desc(weno_l2is_ctx* c) {
   fill_grid_desc(c->n, c->dim, c->dx, c->gamma, c->p, c->g, c->ph);
   c->g.inflow = c->inflow;
+  if (c->ygh) {
+    const size_t side = (size_t)3 * 4 * c->n[0];
+    c->g.ygh[0] = c->p.bc[2] >= WL2_BC_STATE_WALL ? c->ygh : nullptr;
+    c->g.ygh[1] = c->p.bc[3] >= WL2_BC_STATE_WALL ? c->ygh + side : nullptr;
+  }
+}
+
+bool has_state_sides(const weno_l2is_params* p, int dim) {
+  return dim == 2 && (p->bc[2] >= WL2_BC_STATE_WALL || p->bc[3] >= WL2_BC_STATE_WALL);
+}
+
+// Ghost rows of the y state sides for the state Uk, at the stage time
+// t0 + tc dt (tc < 0: the clock's t).
+hipError_t fill_yghosts(const weno_l2is_ctx* c, const double* Uk, double tc) {
+  if (!c->ygh) return hipSuccess;
+  YGhostRule r;
+  for (int s = 0; s < 2; ++s)
+    for (int v = 0; v < 4; ++v) r.state[s][v] = c->p.bstate[s][v];
+  for (int i = 0; i < 4; ++i) r.geom[i] = c->p.bgeom[i];
+  const long long n = 2ll * 3 * c->n[0];
+  hipLaunchKernelGGL(ghost_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, Uk,
+                     c->g, c->ctl, tc, c->dx, r, const_cast<double*>(c->g.ygh[0]),
+                     const_cast<double*>(c->g.ygh[1]));
+  return hipGetLastError();
 }
 
 // An inflow side whose ghost state has not been given yet.
@@ -347,6 +372,7 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
 // dU/dt of the state Uk into out (WRITE then ACCUM over directions).
 hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
   hipError_t e;
+  if ((e = fill_yghosts(c, Uk, -1.0)) != hipSuccess) return e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
   if (use_row(c)) return launch_row(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
@@ -361,8 +387,9 @@ hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
 // 1D/2D paths): the stage kernels also fold the CFL maximum of `out` into
 // the control word.
 hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, double* out,
-                 double ra, double rb, bool fold_cfl = false) {
+                 double ra, double rb, double tc, bool fold_cfl = false) {
   hipError_t e;
+  if ((e = fill_yghosts(c, Uk, tc)) != hipSuccess) return e;
   if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
   if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
@@ -376,13 +403,15 @@ hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, dou
 
 hipError_t rk3(const weno_l2is_ctx* c, double* U, bool fold_cfl = false) {
   hipError_t e;
-  if ((e = stage(c, U, nullptr, c->U1, 0.0, 1.0)) != hipSuccess) return e;
-  if ((e = stage(c, c->U1, U, c->U2, 0.75, 0.25)) != hipSuccess) return e;
-  return stage(c, c->U2, U, U, 1.0 / 3.0, 2.0 / 3.0, fold_cfl);
+  // the stages at the times t0, t0 + dt, t0 + dt/2 of the Shu-Osher form
+  if ((e = stage(c, U, nullptr, c->U1, 0.0, 1.0, 0.0)) != hipSuccess) return e;
+  if ((e = stage(c, c->U1, U, c->U2, 0.75, 0.25, 1.0)) != hipSuccess) return e;
+  return stage(c, c->U2, U, U, 1.0 / 3.0, 2.0 / 3.0, 0.5, fold_cfl);
 }
 
 std::mutex g_cache_mu;
-std::map<std::tuple<int, int, int, int>, weno_l2is_ctx*> g_cache;
+// key: grid shape, device, whether the context holds y state-side ghost rows
+std::map<std::tuple<int, int, int, int, int>, weno_l2is_ctx*> g_cache;
 
 }  // namespace
 
@@ -499,6 +528,10 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
   if (ok && p->bc[0] == WL2_BC_INFLOW)
     ok = hipMalloc(&c->inflow, sizeof(double) * c->nvar * (size_t)ny * nz) == hipSuccess;
   if (ok) c->g.inflow = c->inflow;
+  // y state sides (2D): three ghost rows per side, refilled every stage
+  if (ok && has_state_sides(p, c->dim))
+    ok = hipMalloc(&c->ygh, sizeof(double) * 2 * 3 * 4 * (size_t)nx) == hipSuccess;
+  if (ok) fill_desc(c);
   // (cell list: counts and offsets; face lists: counts and offsets over
   // three directions)
   if (ok && c->dim == 3)
@@ -516,6 +549,7 @@ int weno_l2is_create(int nx, int ny, int nz, double dx, double gamma, const weno
     (void)hipFree(c->flist);
     (void)hipFree(c->counts);
     (void)hipFree(c->inflow);
+    (void)hipFree(c->ygh);
     (void)hipFree(c->ctl);
     delete c;
     (void)hipGetLastError();
@@ -539,6 +573,7 @@ void weno_l2is_destroy(weno_l2is_ctx* c) {
   (void)hipFree(c->flist);
   (void)hipFree(c->counts);
   (void)hipFree(c->inflow);
+  (void)hipFree(c->ygh);
   (void)hipFree(c->ctl);
   delete c;
 }
@@ -598,7 +633,7 @@ int weno_l2is_rhs(const double* U, int nx, int ny, int nz, double dx, double gam
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return WL2_E_HIP;
   std::lock_guard<std::mutex> lk(g_cache_mu);
-  auto key = std::make_tuple(nx, ny, nz, dev);
+  auto key = std::make_tuple(nx, ny, nz, dev, has_state_sides(params, grid_dim(ny, nz)) ? 1 : 0);
   weno_l2is_ctx* c = nullptr;
   auto it = g_cache.find(key);
   if (it == g_cache.end()) {
@@ -622,6 +657,7 @@ int weno_l2is_rhs_noalloc(const double* U, int nx, int ny, int nz, double dx, do
   if (rc) return rc;
   if (params->bc[0] == WL2_BC_INFLOW) return WL2_E_BC;  // no context to hold its state
   const int dim = nz > 1 ? 3 : (ny > 1 ? 2 : 1);
+  if (has_state_sides(params, dim)) return WL2_E_BC;  // no scratch for their ghost rows
   const size_t nc = (size_t)nx * ny * nz;
   if (overlaps(U, dUdt, (size_t)(2 + dim) * nc)) return WL2_E_PARAM;
   const int n[3] = {nx, ny, nz};
@@ -770,6 +806,7 @@ int weno_l2is_face_debug(weno_l2is_ctx* c, const double* U, int dir, unsigned ch
   const long long blocks = (nface + 255) / 256;
   if (blocks > 0x7fffffffLL) return WL2_E_SHAPE;
   const dim3 gr((unsigned)blocks), bl(256);
+  if (fill_yghosts(c, U, -1.0) != hipSuccess) return WL2_E_HIP;
 #define WL2_DBG(NV, D) \
   hipLaunchKernelGGL((face_debug_kernel<NV, D>), gr, bl, 0, c->stream, U, c->g, c->ph, flags, sigma, nface)
   switch (c->nvar * 3 + dir) {

@@ -1,6 +1,7 @@
 // Host-side construction of the kernel descriptors of one grid, shared by the
 // single-grid context and the batch engine so both derive identical constants.
 #pragma once
+#include <cmath>
 #include "../../include/weno_l2is.h"
 #include "wl2_device.hpp"
 
@@ -20,6 +21,7 @@ inline void fill_grid_desc(const int n[3], int dim, double dx, double gamma,
   g.stride[2] = (long long)n[0] * n[1];
   g.ncell = (long long)n[0] * n[1] * n[2];
   g.inflow = nullptr;  // set by the owner of the inflow state
+  g.ygh[0] = g.ygh[1] = nullptr;  // set by the owner of the y ghost rows
   ph.gamma = gamma;
   ph.gm1 = gamma - 1.0;
   ph.dx = dx;
@@ -52,11 +54,16 @@ inline int validate_grid(int nx, int ny, int nz, double dx, double gamma,
     return WL2_E_PARAM;
   if (p->split < 0 || p->split > 2 || p->hybrid < 0 || p->hybrid > 3) return WL2_E_PARAM;
   if (p->weights < WL2_W_L2IS || p->weights > WL2_W_IS_B01) return WL2_E_PARAM;
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(p->bgeom[i])) return WL2_E_PARAM;
   const int dim = grid_dim(ny, nz);
   const int n[3] = {nx, ny, nz};
   for (int d = 0; d < dim; ++d) {
     const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
-    if (lo < 0 || lo > 3 || hi < 0 || hi > 2) return WL2_E_BC;
+    if (lo < 0 || lo > 5 || hi < 0 || hi > 5 || hi == WL2_BC_INFLOW) return WL2_E_BC;
+    // state sides: the y sides of a 2D grid only
+    const bool st = lo >= WL2_BC_STATE_WALL || hi >= WL2_BC_STATE_WALL;
+    if (st && (d != 1 || dim != 2)) return WL2_E_BC;
     // inflow: the x- side of a 1D or 2D grid only
     if (lo == WL2_BC_INFLOW && (d != 0 || dim == 3)) return WL2_E_BC;
     if ((lo == WL2_BC_PERIODIC) != (hi == WL2_BC_PERIODIC)) return WL2_E_BC;

@@ -27,7 +27,8 @@
 
 namespace wl2 {
 
-enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3,
+       BC_STATE_WALL = 4, BC_STATE_FRONT = 5 };
 enum { SPLIT_LLF = 0, SPLIT_LF = 1, SPLIT_ROE = 2 };
 enum { HYB_PER_FIELD = 0, HYB_PER_FACE = 1, HYB_WENO_ONLY = 2, HYB_LINEAR_ONLY = 3 };
 // weights of the WENO branch: regularized Eq.(28), original WENO-IS Eq.(8),
@@ -46,6 +47,10 @@ struct KGrid {
   // x- inflow side: the conserved state of the three ghosts of each x line,
   // [nvar][ny*nz] (null for every other boundary rule)
   const double* inflow;
+  // y sides of a 2D grid with state ghosts (BC_STATE_WALL, BC_STATE_FRONT):
+  // their three ghost rows, [layer][nvar][nx] (layer 0 next to the grid),
+  // filled before every stage by ghost_fill_kernel (null otherwise)
+  const double* ygh[2];
 };
 
 // Physical and scheme constants passed by value.
@@ -72,6 +77,7 @@ struct StepCtl {
   unsigned int steps;            // clock steps taken (steps that advanced t)
   double dt;                     // dt of the step in flight
   double t;                      // simulated time after the step in flight
+  double t0;                     // simulated time at the start of the step in flight
   double t_end;                  // > 0: clip the clock to it
   unsigned long long lf_bits[3][5];  // global LF speeds (raw bits) per direction, field
   unsigned int list_n[2];        // entries in the nonlinear-correction list: consecutive
@@ -189,16 +195,32 @@ __device__ __forceinline__ int ghost_index(int k, int n, int lo, int hi, bool& f
   if (k >= 0 && k < n) return k;
   if (k < 0) {
     if (lo == BC_PERIODIC) { int r = k % n; return r < 0 ? r + n : r; }
-    // inflow ghosts are taken from KGrid::inflow by the caller; the index
-    // returned is an in-grid one
-    if (lo == BC_TRANSMISSIVE || lo == BC_INFLOW) return 0;
+    // inflow and state ghosts are taken from KGrid::inflow / ygh by the
+    // caller; the index returned is an in-grid one
+    if (lo == BC_TRANSMISSIVE || lo == BC_INFLOW || lo >= BC_STATE_WALL) return 0;
     flip = true;
     return -1 - k;
   }
   if (hi == BC_PERIODIC) return k % n;
-  if (hi == BC_TRANSMISSIVE) return n - 1;
+  if (hi == BC_TRANSMISSIVE || hi >= BC_STATE_WALL) return n - 1;
   flip = true;
   return 2 * n - 1 - k;
+}
+
+// Is line position y (outside 0..ny-1) a state ghost of a y side?
+__device__ __forceinline__ bool is_yghost(const KGrid& g, int y) {
+  return (y < 0 && g.bc_lo[1] >= BC_STATE_WALL) || (y >= g.n[1] && g.bc_hi[1] >= BC_STATE_WALL);
+}
+
+// State ghost at column x, row y (outside the grid) of a 2D grid.
+template <int NV>
+__device__ __forceinline__ void load_yghost(const KGrid& g, long long x, int y, double (&u)[NV]) {
+  const int side = y < 0 ? 0 : 1;
+  int layer = y < 0 ? -1 - y : y - g.n[1];
+  layer = layer > 2 ? 2 : layer;
+  const double* b = g.ygh[side] + (long long)layer * NV * g.n[0];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = b[(long long)v * g.n[0] + x];
 }
 
 // Ghost state of the x- inflow side for x line `row` (= y + ny*z).
@@ -222,6 +244,8 @@ __device__ __forceinline__ void load_state(const double* __restrict__ U, const K
   if (flip) u[1 + DIR] = -u[1 + DIR];
   // x lines start at cell offset row * nx
   if (DIR == 0 && k < 0 && g.bc_lo[0] == BC_INFLOW) load_inflow<NV>(g, base / g.n[0], u);
+  // y lines of a 2D grid start at cell offset x
+  if (DIR == 1 && NV == 4 && (k < 0 || k >= g.n[1]) && is_yghost(g, k)) load_yghost<NV>(g, base, k, u);
 }
 
 // ---------------------------------------------------------------- cells

@@ -363,6 +363,8 @@ __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, cons
     if (flip[m]) u[m][1 + DIR] = -u[m][1 + DIR];
     if (DIR == 0 && c0 + m < 0 && g.bc_lo[0] == BC_INFLOW)
       load_inflow<NV>(g, y + (long long)g.n[1] * z, u[m]);
+    if (DIR == 1 && NV == 4 && (c0 + m < 0 || c0 + m >= g.n[1]) && is_yghost(g, c0 + m))
+      load_yghost<NV>(g, x, c0 + m, u[m]);
     make_lrec<NV>(u[m], ph, w[m]);
   }
   const WinSrc<NV> src{w[0], w[1], w[2], w[3], w[4], w[5]};

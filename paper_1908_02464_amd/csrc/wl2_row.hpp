@@ -126,6 +126,8 @@ __device__ __forceinline__ void row_load_raw(const double* __restrict__ U, const
   const long long off = xy + (long long)iy * g.stride[1];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
+  // state ghosts of a y side (2D grids: xy is the column's x)
+  if (NV == 4 && (y < 0 || y >= g.n[1]) && is_yghost(g, y)) load_yghost<NV>(g, xy, y, u);
 }
 
 template <int NV>

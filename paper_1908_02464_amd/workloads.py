@@ -105,6 +105,42 @@ def mach2000_jet(nx=640, ny=160, gamma=JET_GAMMA):
     return U0, dx, np.ascontiguousarray(inflow.reshape(4, ny))
 
 
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+DMR_POST = (8.0, 7.145, -4.125, 116.8333)
+DMR_X0, DMR_SLOPE = 0.1667, 1.732
+
+
+def double_mach(nx=512, ny=128, gamma=GAMMA):
+    """Double Mach reflection (Sec. 4.5) on [0,4] x [0,1] (nx = 4 ny): the
+    Mach 10 shock y = 1.732 (x - 0.1667) with the pre-shock gas (1.4, 0, 0,
+    1) below-right of it and (8, 7.145, -4.125, 116.8333) above-left (the
+    printed states; a cell takes the pre-shock state when its centre is on
+    or below the line).  Returns (U0, dx, params): the boundary settings of
+    the run, keyword arguments of the oracle's and the library's parameter
+    constructors: post-shock inflow on the left; outflow on the right; the
+    bottom a wall from x = 0.1667 on and the post-shock state left of it;
+    the top the exact position of the moving shock, x = 0.1667 + (y + 20 t)
+    / 1.732 (the shock moves at 10 normal to itself into gas with sound speed
+    1), post-shock left of it and pre-shock right of it."""
+    assert nx == 4 * ny
+    x, dx = centres(nx, 0.0, 4.0)
+    y, _ = centres(ny, 0.0, 1.0)
+    X, Y = np.meshgrid(x, y)
+    pre = Y <= DMR_SLOPE * (X - DMR_X0)
+    prim = [np.where(pre, a, b) for a, b in zip(DMR_PRE, DMR_POST)]
+    U0 = conserved(prim[0], [prim[1], prim[2]], prim[3], gamma).reshape(4, 1, ny, nx)
+    post = conserved(np.array(DMR_POST[0]), [np.array(DMR_POST[1]), np.array(DMR_POST[2])],
+                     np.array(DMR_POST[3]), gamma).ravel()
+    pre_s = conserved(np.array(DMR_PRE[0]), [np.array(DMR_PRE[1]), np.array(DMR_PRE[2])],
+                      np.array(DMR_PRE[3]), gamma).ravel()
+    inflow = np.ascontiguousarray(np.repeat(post.reshape(4, 1), ny, axis=1))
+    params = {"bc": [3, 1, 4, 5, 1, 1],
+              "bstate": [list(post) + [0.0], list(pre_s) + [0.0]],
+              # wall from x = 0.1667; front x0, dx/dy, dx/dt
+              "bgeom": [DMR_X0, DMR_X0, 1.0 / DMR_SLOPE, 20.0 / DMR_SLOPE]}
+    return np.ascontiguousarray(U0), dx, params, inflow
+
+
 def shu_osher(n=1600, gamma=GAMMA):
     """Mach-3 shock / entropy wave on [-5,5]: shocked state for x < -4."""
     x, dx = centres(n, -5.0, 5.0)

@@ -1214,3 +1214,149 @@ def test_mach2000_jet_full_run(orc, capi, name, kw):
     say(f"    steps={k} t={t!r} status={st} min rho={rho.min():.3e} min p={pr.min():.3e}")
     assert st == 0 and t == 1e-3
     assert rho.min() > 0 and pr.min() > 0
+
+
+# ------------------------------------------- double Mach reflection (Sec. 4.5)
+def _dmr_case(orc, capi, nx, ny, **kw):
+    U, dx, prm, inf = w.double_mach(nx, ny)
+    prm = dict(prm, **kw)
+    po = orc.params(nx, ny, 1, dx, inflow=inf, **prm)
+    pg = capi.params_default(nx, ny, 1, dx, **prm)
+    return U, dx, po, pg, inf
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("t", [0.0, 0.031])
+def test_dmr_rhs_parity(orc, capi, path, t):
+    """Right-hand side with the state sides of the double Mach reflection
+    (a wall from x = 0.1667 on, post-shock ghosts left of it; the exact
+    moving shock on the top at the clock's time), through the row kernel
+    and the sweeps, on the initial state and on a state the oracle has
+    advanced."""
+    import torch
+    say(f"[dmr rhs] path={path} t={t}")
+    U, dx, po, pg, inf = _dmr_case(orc, capi, 128, 32)
+    if t > 0:
+        tt, n, st = orc.run(U, dx, G, po, t)
+        assert st == 0 and tt == t
+    po.time = t
+    ref = orc.rhs(U, dx, G, po)
+    ctx = capi.Context(128, 32, 1, dx, G, pg)
+    if path:
+        ctx.tune(path=capi.PATH_SWEEPS)
+    ctx.set_inflow(to_dev(inf))
+    ctx.set_time(t)
+    Ud = to_dev(U)
+    out = torch.full_like(Ud, float("nan"))
+    ctx.rhs(Ud, out)
+    torch.cuda.synchronize()
+    ctx.close()
+    dt, _ = orc.cfl_dt(U, dx, G)
+    err = rhs_err(to_host(out), ref, U, dt)
+    say(f"    rhs err = {err:.3e}")
+    assert err <= 1e-12
+
+
+def _oracle_steps(orc, U, dx, po, t_end, noise=0.0, dts=None, seed=0):
+    """The oracle's run from po.time to t_end step by step (its CFL steps,
+    clipped to t_end), or along the given dt sequence; with noise > 0 the
+    state is multiplied by (1 + noise N(0,1)) after every step.  Returns the
+    final state and the dt sequence."""
+    V = U.copy()
+    rng = np.random.default_rng(1000 + seed)
+    t, out = po.time, []
+    k = 0
+    while (dts is None and t < t_end) or (dts is not None and k < len(dts)):
+        po.time = t
+        if dts is None:
+            dt, st = orc.cfl_dt(V, dx, G, po.cfl)
+            dt = min(dt, t_end - t)
+        else:
+            dt = dts[k]
+        _, st = orc.step(V, dx, G, po, dt)
+        assert st == 0
+        if noise > 0:
+            V *= 1.0 + noise * rng.standard_normal(V.shape)
+        out.append(dt)
+        t += dt
+        k += 1
+    po.time = 0.0
+    return V, out
+
+
+@pytest.mark.parametrize("shape", [(128, 32), (256, 64)])
+def test_dmr_full_run_parity(orc, capi, shape):
+    """The double Mach reflection to the paper's t = 0.2 on the device
+    clock (the top boundary follows the stage times) against the oracle run
+    to the same time: the same step count, the state to the 100-step bar,
+    or where the run's conditioning puts that out of reach (the roll-ups of
+    the slip line and the wall jet at 256 x 64), twice the largest spread of
+    the oracle's own run under per-step relative noise of the size of one
+    GPU step's distance from one oracle step (two seeds)."""
+    import torch
+    nx, ny = shape
+    say(f"[dmr full run] {nx}x{ny} to t=0.2")
+    U, dx, po, pg, inf = _dmr_case(orc, capi, nx, ny)
+    Uo = U.copy()
+    t_o, n_o, st = orc.run(Uo, dx, G, po, 0.2)
+    assert st == 0 and t_o == 0.2
+    ctx = capi.Context(nx, ny, 1, dx, G, pg)
+    ctx.set_inflow(to_dev(inf))
+    ctx.set_time(0.0)
+    Ud = to_dev(U)
+    while ctx.time()[0] < 0.2 and ctx.status() == 0:
+        ctx.advance(Ud, 256, 0.2)
+    t_g, _, k = ctx.clock()
+    stg = ctx.status()
+    ctx.close()
+    torch.cuda.synchronize()
+    err = z20(to_host(Ud), Uo)
+    say(f"    steps oracle={n_o} gpu={k} z20={err:.3e}")
+    assert stg == 0 and t_g == 0.2 and k == n_o
+    if err > 1e-10:
+        ctx = capi.Context(nx, ny, 1, dx, G, pg)
+        ctx.set_inflow(to_dev(inf))
+        ctx.set_time(0.0)
+        U1 = to_dev(U)
+        ctx.advance(U1, 1, 0.2)
+        torch.cuda.synchronize()
+        ctx.close()
+        V1, _ = _oracle_steps(orc, U, dx, po, 0.2, dts=[orc.cfl_dt(U, dx, G, 0.5)[0]])
+        d1 = max(z20(to_host(U1), V1), 2.2e-16)
+        Vr, dts = _oracle_steps(orc, U, dx, po, 0.2)
+        spread = max(z20(_oracle_steps(orc, U, dx, po, 0.2, noise=d1, dts=dts, seed=s)[0], Vr)
+                     for s in range(2))
+        say(f"    one-step distance d1 = {d1:.3e}; oracle spread under d1 noise per step = "
+            f"{spread:.3e}; err / spread = {err / spread:.2f} (bar 2)")
+        assert err <= 2.0 * spread
+
+
+def test_dmr_paper_grid_run(capi):
+    """The paper's 512 x 128 grid to t = 0.2 on the device (the workload of
+    Table 1): physical throughout, the incident shock on the top row where
+    the exact motion puts it, the densest gas near the paper's largest
+    contour (20.9), the pre-shock gas ahead of the shock untouched."""
+    import torch
+    nx, ny = 512, 128
+    say(f"[dmr paper grid] {nx}x{ny} to t=0.2")
+    U, dx, prm, inf = w.double_mach(nx, ny)
+    ctx = capi.Context(nx, ny, 1, dx, G, capi.params_default(nx, ny, 1, dx, **prm))
+    ctx.set_inflow(to_dev(inf))
+    ctx.set_time(0.0)
+    Ud = to_dev(U)
+    while ctx.time()[0] < 0.2 and ctx.status() == 0:
+        ctx.advance(Ud, 512, 0.2)
+    t, _, k = ctx.clock()
+    st = ctx.status()
+    ctx.close()
+    rho = to_host(Ud)[0, 0]
+    top = rho[-1]
+    i = np.where((top[:-1] > 4.7) & (top[1:] <= 4.7))[0][-1]
+    xs = (i + 1.0) * dx
+    exact = w.DMR_X0 + (1.0 - 0.5 * dx + 20.0 * 0.2) / w.DMR_SLOPE
+    say(f"    steps={k} status={st} rho max={rho.max():.3f} min={rho.min():.4f} "
+        f"top shock x={xs:.4f} exact={exact:.4f}")
+    assert st == 0 and t == 0.2
+    assert abs(xs - exact) < 1.5 * dx
+    assert 15.0 < rho.max() < 25.0 and rho.min() > 1.39
+    assert np.all(np.abs(rho[:, -16:] - 1.4) < 1e-6)
