@@ -49,6 +49,38 @@ def test_wall_side_reduces_to_reflective_and_to_prescribed_state(orc):
     assert not np.array_equal(ra, orc.rhs(U, dx, G, pw))
 
 
+def test_state_sides_equal_a_grid_extended_by_their_ghost_rows(orc):
+    """The rows next to the state sides see exactly the grid extended by
+    three rows below and above, holding the ghost states of the definition:
+    post-shock below the cells centred left of 0.1667 and the mirror image
+    elsewhere; above, post- or pre-shock by the front's position at each
+    ghost centre at time t."""
+    nx, ny = 128, 32
+    U, dx, prm, inf = _dmr(nx, ny)
+    p0 = orc.params(nx, ny, 1, dx, inflow=inf, **prm)
+    t = 0.013
+    orc.run(U, dx, G, p0, t)
+    post, pre = np.array(prm["bstate"][0][:4]), np.array(prm["bstate"][1][:4])
+    x0w, x0, slope, speed = prm["bgeom"]
+    xc = (np.arange(nx) + 0.5) * dx
+    E = np.zeros((4, 1, ny + 6, nx))
+    E[:, :, 3:ny + 3] = U
+    for k in range(3):  # ghost row -1-k below, ny+k above
+        below = U[:, 0, k].copy()
+        below[2] = -below[2]
+        E[:, 0, 2 - k] = np.where(xc < x0w, post[:, None], below)
+        yc = (ny + k + 0.5) * dx
+        E[:, 0, ny + 3 + k] = np.where(xc < x0 + slope * yc + speed * t, post[:, None], pre[:, None])
+    p = orc.params(nx, ny, 1, dx, inflow=inf, thr_L=[4.0, 1.0, 1.0], **prm)
+    p.time = t
+    infe = np.ascontiguousarray(np.repeat(post.reshape(4, 1), ny + 6, axis=1))
+    pe = orc.params(nx, ny + 6, 1, dx, inflow=infe, thr_L=[4.0, 1.0, 1.0],
+                    **dict(prm, bc=[3, 1, 1, 1, 1, 1]))
+    r = orc.rhs(U, dx, G, p)
+    re = orc.rhs(np.ascontiguousarray(E), dx, G, pe)
+    assert np.array_equal(r, re[:, :, 3:ny + 3])
+
+
 def test_front_side_follows_its_time_and_the_stage_times(orc):
     U, dx, prm, inf = _dmr()
     nx, ny = 128, 32
@@ -59,10 +91,17 @@ def test_front_side_follows_its_time_and_the_stage_times(orc):
     moved[1] = prm["bgeom"][1] + prm["bgeom"][3] * t
     q = orc.params(nx, ny, 1, dx, inflow=inf, **dict(prm, bgeom=moved))
     assert np.array_equal(orc.rhs(U, dx, G, p), orc.rhs(U, dx, G, q))
-    # one SSP-RK3 step from t: the stages at t, t + dt, t + dt/2
+    # one SSP-RK3 step from t: the stages at t, t + dt, t + dt/2; t is
+    # chosen so that the front passes a ghost centre of the first ghost row
+    # between t + dt/2 and t + dt
+    x0, slope, speed = prm["bgeom"][1:]
+    dt, _ = orc.cfl_dt(U, dx, G, 0.5)
+    yc = (ny + 0.5) * dx
+    t = ((70 + 0.5) * dx - x0 - slope * yc) / speed - 0.75 * dt
+    p.time = t
     V = U.copy()
-    dt, st = orc.step(V, dx, G, p)
-    assert st == 0
+    dt2, st = orc.step(V, dx, G, p)
+    assert st == 0 and dt2 == dt
     ps = orc.params(nx, ny, 1, dx, inflow=inf, **prm)
     ps.time = t
     U1 = U + dt * orc.rhs(U, dx, G, ps)
@@ -71,6 +110,10 @@ def test_front_side_follows_its_time_and_the_stage_times(orc):
     ps.time = t + 0.5 * dt
     W = (1.0 / 3.0) * U + (2.0 / 3.0) * (U2 + dt * orc.rhs(U2, dx, G, ps))
     assert np.array_equal(V, W)
+    # the third stage at t + dt would differ
+    ps.time = t + dt
+    W3 = (1.0 / 3.0) * U + (2.0 / 3.0) * (U2 + dt * orc.rhs(U2, dx, G, ps))
+    assert not np.array_equal(W3, W)
 
 
 def _crossings(rho, dx, mid):

@@ -24,7 +24,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 PINS = ["tests/test_oracle_scalar.py", "tests/test_oracle_face.py", "tests/test_oracle_readings.py",
-        "tests/test_oracle_solutions.py"]
+        "tests/test_oracle_solutions.py", "tests/test_oracle_dmr.py"]
 
 # (name, file, text as written, planted mistake)
 MUTANTS = [
@@ -67,6 +67,14 @@ MUTANTS = [
     ("beta01_coefficient", "weno_scalar.c",
      "b01 = 13.0 / 12.0 * t1 * t1 + 0.25 * t2 * t2;",
      "b01 = 13.0 / 12.0 * t1 * t1 + 0.5 * t2 * t2;"),
+    # the third RK stage evaluated at t + dt instead of t + dt/2 (a moving
+    # state boundary sees it)
+    ("stage3_time", "solver.c",
+     "ps.time = p->time + 0.5 * dt;", "ps.time = p->time + dt;"),
+    # the moving front's ghosts compared at the wrong height (the interior
+    # row's centre instead of the ghost's)
+    ("front_ghost_height", "solver.c",
+     "yc = (k + 0.5) * g->dx;", "yc = (k - 0.5) * g->dx;"),
     # time step from the largest single-direction speed instead of the sum
     ("cfl_max_over_directions", "solver.c",
      "for (d = 0; d < g->dim; ++d) s += fabs(prim[1 + d]) + prim[5];\n    if (s > smax || s != s)",
