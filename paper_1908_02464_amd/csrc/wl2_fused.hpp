@@ -58,7 +58,8 @@ struct FusedArgs {
   int zc;             // planes per workgroup
   int tiles_x, tiles_y;
   unsigned long long* list;  // cells next to a face that needs the WENO flux
-  unsigned int* list_n;      // number of entries in list
+  unsigned int* list_n;      // entries listed in this stage (all workgroups; zero
+                             // when the stage starts)
   unsigned int* list_clear;  // the next stage's counter, zeroed by the correction kernel
   unsigned int* counts;      // entries each workgroup listed in its list region
   unsigned int* offs;        // exclusive prefix sums of counts (nreg + 1 values)
@@ -85,8 +86,9 @@ struct FusedArgs {
 // workgroup's in-grid cells (only the last tile along x, the last tile row
 // and the last z chunk are partial, so every region before a given one is
 // full-sized).  First list index of the region of logical tile r.
-// Regions up to which the correction kernel forms the list offsets itself
-// (in LDS); beyond, a one-workgroup scan kernel writes them.
+// Regions up to which a correction kernel keeps the list offsets in LDS
+// (the per-cell kernel forms them there itself; beyond, a one-workgroup scan
+// kernel writes them to global memory, as it always does for face lists).
 constexpr int SCAN_LDS = 8192;
 
 __device__ __forceinline__ long long list_region_start(const FusedArgs& a, const KGrid& g, int r) {
@@ -554,7 +556,12 @@ __global__ __launch_bounds__(FT_THREADS, WPE) void fused3d_kernel(FusedArgs a, K
                    ox == cols_v - 1 && ttx == a.tiles_x - 1, oy == rows_v - 1 && tty == a.tiles_y - 1);
     }
     __syncthreads();  // every append of the workgroup is counted
-    if (t == 0) a.counts[logical] = s_cnt;
+    if (t == 0) {
+      a.counts[logical] = s_cnt;
+      // the stage's total (zero at the stage's start): the correction
+      // kernels return at once when nothing was listed
+      if (s_cnt != 0u) atomicAdd(a.list_n, s_cnt);
+    }
     if (flists && t < 3) a.counts_f[t * (int)gridDim.x + logical] = s_fcnt[t];
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
@@ -598,6 +605,18 @@ __device__ __forceinline__ int find_segment(const unsigned int* offs, int nseg, 
   return lo;
 }
 
+// The list offsets (nseg + 1 values written by list_scan_kernel) where a
+// kernel looks them up: in global memory (L2) when no lane takes more than
+// one of the n entries, else copied into LDS once per block (up to
+// SCAN_LDS segments), so that the bisection of each entry runs in LDS.
+__device__ __forceinline__ const unsigned int* stage_offsets(const unsigned int* offs, int nseg,
+                                                             unsigned int n, unsigned int* soffs) {
+  if (n <= gridDim.x * blockDim.x || nseg > SCAN_LDS) return offs;
+  for (int r = threadIdx.x; r <= nseg; r += blockDim.x) soffs[r] = offs[r];
+  __syncthreads();
+  return soffs;
+}
+
 // Per listed cell: add the nonlinear part of the flux of its flagged faces,
 // summed in the fixed order x-, x+, y-, y+, z-, z+, to the output (scaled by
 // rk_b dt for a stage, 1 for dU/dt); eight lanes per cell (one per face) for
@@ -608,7 +627,9 @@ __device__ __forceinline__ int find_segment(const unsigned int* offs, int nseg, 
 // spills 104 bytes): the stencil loads of a face are latency-bound, and at
 // 256^3 two waves beat one by 16 % once shocklets form (3.18 against 3.78
 // ms per step at 2.9 % WENO face-fields) and by 4 % in the smooth regime.
-template <int OUT, int SPLIT, int HYB>
+// W: the weighting of the reconstruction fixed at compile time (W_*), or -1
+// to read it at run time.
+template <int OUT, int SPLIT, int HYB, int W>
 __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
   constexpr int GRP = 8;
@@ -630,8 +651,8 @@ __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g
     const int y = (int)((off / g.n[0]) % g.n[1]);
     const int z = (int)(off / g.stride[2]);
     double acc[NV];
-    if (grouped) grouped_correction<NV, GRP, SPLIT, HYB>(a.Uk, g, ph, a.ctl, x, y, z, cm, acc);
-    else serial_correction<NV, SPLIT, HYB>(a.Uk, g, ph, a.ctl, x, y, z, cm, acc);
+    if (grouped) grouped_correction<NV, GRP, SPLIT, HYB, W>(a.Uk, g, ph, a.ctl, x, y, z, cm, acc);
+    else serial_correction<NV, SPLIT, HYB, W>(a.Uk, g, ph, a.ctl, x, y, z, cm, acc);
     if (!grouped || (threadIdx.x % GRP) == 0) {
       double un[NV];
 #pragma unroll
@@ -657,7 +678,7 @@ __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g
     const unsigned int step = grouped ? threads / GRP : threads;
     for (unsigned int i = grouped ? tid / GRP : tid; i < n; i += step)
       fix_one(((unsigned long long)i << 8) | 0x3full, grouped);
-  } else {
+  } else if (*a.list_n != 0u) {
     // the entries of all list regions as one index space: entry i lies in
     // the region r with offs[r] <= i < offs[r + 1], found by bisection.  Up
     // to SCAN_LDS regions every block forms the offsets in LDS from the
@@ -684,27 +705,25 @@ __global__ __launch_bounds__(128, 2) void weno_fix3d_kernel(FusedArgs a, KGrid g
 }
 
 // Face lists, face-once corrections: every entry of the three face lists
-// (taken as one index space over (direction, region), the offsets in LDS or
-// written by list_scan_kernel) gives one face, whose change of flux (WENO
+// (taken as one index space over (direction, region), the offsets written by
+// list_scan2_kernel) gives one face, whose change of flux (WENO
 // minus linear, Eq.(20)-(28), (33)) goes to D[face][v] of its direction.
 // One face per lane, and the lanes of a wavefront take consecutive entries,
 // so that a wavefront runs faces of one direction (except where the x list
 // meets the y list and the y list the z list).  The change depends on the
 // face only: the same bits as weno_fix3d_kernel computes for either cell.
-template <int OUT, int SPLIT, int HYB>
+// W: the weighting of the reconstruction fixed at compile time (W_*), or -1
+// to read it at run time.
+template <int OUT, int SPLIT, int HYB, int W>
 __global__ __launch_bounds__(128, 2) void weno_flist3d_kernel(FusedArgs a, KGrid g, KPhys ph) {
   constexpr int NV = 5;
   if (OUT == OUT_RK && !(a.ctl->dt > 0.0)) return;
+  if (*a.list_n == 0u) return;  // no cell listed in this stage
   const int nreg = a.tiles_x * a.tiles_y * ((g.n[2] + a.zc - 1) / a.zc);
   const int nseg = 3 * nreg;
   __shared__ unsigned int soffs[SCAN_LDS + 1];
-  __shared__ unsigned int spart[128];
-  const unsigned int* offs = a.offs_f;
-  if (nseg <= SCAN_LDS) {
-    block_offsets(a.counts_f, nseg, soffs, spart);
-    offs = soffs;
-  }
-  const unsigned int n = offs[nseg];
+  const unsigned int n = a.offs_f[nseg];
+  const unsigned int* offs = stage_offsets(a.offs_f, nseg, n, soffs);
   const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz;
   const unsigned int threads = gridDim.x * blockDim.x;
@@ -725,13 +744,13 @@ __global__ __launch_bounds__(128, 2) void weno_flist3d_kernel(FusedArgs a, KGrid
     double dF[NV];
     double* D;
     if (d == 0) {
-      face_delta<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, z, 0, dF);
+      face_delta<NV, 0, SPLIT, HYB, W>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, z, 0, dF);
       D = a.D;
     } else if (d == 1) {
-      face_delta<NV, 1, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, z, 0, dF);
+      face_delta<NV, 1, SPLIT, HYB, W>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, z, 0, dF);
       D = a.D + NV * nfx;
     } else {
-      face_delta<NV, 2, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[2], x, y, z, 0, dF);
+      face_delta<NV, 2, SPLIT, HYB, W>(a.Uk, g, ph, a.ctl->lf_bits[2], x, y, z, 0, dF);
       D = a.D + NV * (nfx + nfy);
     }
 #pragma unroll
@@ -754,15 +773,11 @@ __global__ __launch_bounds__(256) void weno_sumlist3d_kernel(FusedArgs a, KGrid 
     if (!(dt > 0.0)) return;
     scale = a.rk_b * dt;
   }
+  if (*a.list_n == 0u) return;  // no cell listed in this stage
   const int nreg = a.tiles_x * a.tiles_y * ((g.n[2] + a.zc - 1) / a.zc);
   __shared__ unsigned int soffs[SCAN_LDS + 1];
-  __shared__ unsigned int spart[256];
-  const unsigned int* offs = a.offs;
-  if (nreg <= SCAN_LDS) {
-    block_offsets(a.counts, nreg, soffs, spart);
-    offs = soffs;
-  }
-  const unsigned int n = offs[nreg];
+  const unsigned int n = a.offs[nreg];
+  const unsigned int* offs = stage_offsets(a.offs, nreg, n, soffs);
   const long long nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz;
   const double* Dd[3] = {a.D, a.D + NV * nfx, a.D + NV * (nfx + nfy)};
@@ -810,7 +825,9 @@ __global__ __launch_bounds__(256) void weno_sumlist3d_kernel(FusedArgs a, KGrid 
 // more face along DIR (face f lies between cells f-1 and f).  A face's change
 // depends on its position only, so it equals what the per-cell kernel
 // computes for either of its cells.
-template <int OUT, int DIR, int SPLIT, int HYB>
+// W: the weighting of the reconstruction fixed at compile time (W_*), or -1
+// to read it at run time.
+template <int OUT, int DIR, int SPLIT, int HYB, int W>
 __global__ __launch_bounds__(128) void weno_face3d_kernel(FusedArgs a, KGrid g, KPhys ph, double* D) {
   constexpr int NV = 5;
   if (OUT == OUT_RK && !(a.ctl->dt > 0.0)) return;
@@ -822,7 +839,7 @@ __global__ __launch_bounds__(128) void weno_face3d_kernel(FusedArgs a, KGrid g, 
     const int y = (int)((i / ex) % ey);
     const int z = (int)(i / (ex * ey));
     double dF[NV];
-    face_delta<NV, DIR, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[DIR], x, y, z, 0, dF);
+    face_delta<NV, DIR, SPLIT, HYB, W>(a.Uk, g, ph, a.ctl->lf_bits[DIR], x, y, z, 0, dF);
 #pragma unroll
     for (int v = 0; v < NV; ++v) D[v * nf + i] = dF[v];
   }
@@ -886,9 +903,8 @@ __global__ __launch_bounds__(256) void weno_sum3d_kernel(FusedArgs a, KGrid g, K
 // Exclusive prefix sums of the per-workgroup list counts: offs[r] = entries
 // of the regions before r, offs[nreg] = all entries.  One workgroup of 1024
 // threads, each summing a contiguous run of counts.
-static __global__ __launch_bounds__(1024) void list_scan_kernel(const unsigned int* counts, int nreg,
-                                                                unsigned int* offs) {
-  __shared__ unsigned int part[1024];
+__device__ __forceinline__ void scan_counts(const unsigned int* counts, int nreg, unsigned int* offs,
+                                            unsigned int* part) {
   const int t = threadIdx.x;
   const int per = (nreg + 1023) / 1024;
   const int b = t * per, e = min(b + per, nreg);
@@ -909,6 +925,23 @@ static __global__ __launch_bounds__(1024) void list_scan_kernel(const unsigned i
     run += counts[r];
   }
   if (t == 1023) offs[nreg] = part[1023];
+}
+
+static __global__ __launch_bounds__(1024) void list_scan_kernel(const unsigned int* counts, int nreg,
+                                                                unsigned int* offs) {
+  __shared__ unsigned int part[1024];
+  scan_counts(counts, nreg, offs, part);
+}
+
+// Both offset arrays of the face-list corrections (cells: counts -> offs;
+// faces: counts_f -> offs_f over the 3 nreg (direction, region) segments) in
+// one launch; nothing to do when the stage listed no cell.
+static __global__ __launch_bounds__(1024) void list_scan2_kernel(FusedArgs a, int nreg) {
+  __shared__ unsigned int part[1024];
+  if (*a.list_n == 0u) return;
+  scan_counts(a.counts, nreg, a.offs, part);
+  __syncthreads();
+  scan_counts(a.counts_f, 3 * nreg, a.offs_f, part);
 }
 
 [[maybe_unused]] static __global__ void reset_list_kernel(unsigned int* list_n) {

@@ -87,7 +87,7 @@ size_t fused3d_face_doubles(const int n[3]) {
 
 // Every face WENO with a face buffer: each face's change once (three
 // launches, one per direction), then the per-cell sums.
-template <int O>
+template <int O, int W>
 static hipError_t fix_face_once(const FusedLaunch& L, const FusedArgs& a) {
   const long long nx = L.n[0], ny = L.n[1], nz = L.n[2];
   const long long nfx = (nx + 1) * ny * nz, nfy = nx * (ny + 1) * nz, nfz = nx * ny * (nz + 1);
@@ -98,43 +98,50 @@ static hipError_t fix_face_once(const FusedLaunch& L, const FusedArgs& a) {
     const long long b = (n + t - 1) / t;
     return dim3((unsigned)(b < (1ll << 20) ? b : (1ll << 20)));
   };
-  hipLaunchKernelGGL((weno_face3d_kernel<O, 0, SPLIT_LLF, HYB_WENO_ONLY>), blocks(nfx, 128), dim3(128), 0,
+  hipLaunchKernelGGL((weno_face3d_kernel<O, 0, SPLIT_LLF, HYB_WENO_ONLY, W>), blocks(nfx, 128), dim3(128), 0,
                      L.stream, a, L.g, L.ph, Dx);
-  hipLaunchKernelGGL((weno_face3d_kernel<O, 1, SPLIT_LLF, HYB_WENO_ONLY>), blocks(nfy, 128), dim3(128), 0,
+  hipLaunchKernelGGL((weno_face3d_kernel<O, 1, SPLIT_LLF, HYB_WENO_ONLY, W>), blocks(nfy, 128), dim3(128), 0,
                      L.stream, a, L.g, L.ph, Dy);
-  hipLaunchKernelGGL((weno_face3d_kernel<O, 2, SPLIT_LLF, HYB_WENO_ONLY>), blocks(nfz, 128), dim3(128), 0,
+  hipLaunchKernelGGL((weno_face3d_kernel<O, 2, SPLIT_LLF, HYB_WENO_ONLY, W>), blocks(nfz, 128), dim3(128), 0,
                      L.stream, a, L.g, L.ph, Dz);
   hipLaunchKernelGGL((weno_sum3d_kernel<O>), blocks(nx * ny * nz, 256), dim3(256), 0, L.stream, a, L.g,
                      L.ph, Dx, Dy, Dz);
   return hipGetLastError();
 }
 
-// Face lists: each listed face's change once into the face buffer (one
-// launch for the three lists), then the listed cells' sums.
+// Face lists: the offsets of both lists (one small launch), each listed
+// face's change once into the face buffer (one launch for the three lists),
+// then the listed cells' sums.
 template <int O>
 static hipError_t fix_face_lists(const FusedLaunch& L, const FusedArgs& a) {
   const int sp = L.ph.split, hy = L.ph.hybrid;
+  const bool w0 = L.ph.weights == W_L2IS;
   const int nreg = a.tiles_x * a.tiles_y * ((L.n[2] + a.zc - 1) / a.zc);
-  if (3 * nreg > SCAN_LDS)
-    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts_f, 3 * nreg, a.offs_f);
-  if (nreg > SCAN_LDS)
-    hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts, nreg, a.offs);
-#define WL2_FL(S, H) \
-  hipLaunchKernelGGL((weno_flist3d_kernel<O, S, H>), dim3(1024), dim3(128), 0, L.stream, a, L.g, L.ph)
-  if (sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FL(SPLIT_LLF, HYB_PER_FIELD);
-  else if (sp == SPLIT_ROE && hy == HYB_PER_FIELD) WL2_FL(SPLIT_ROE, HYB_PER_FIELD);
-  else WL2_FL(-1, -1);
+  hipLaunchKernelGGL(list_scan2_kernel, dim3(1), dim3(1024), 0, L.stream, a, nreg);
+#define WL2_FL(S, H, W) \
+  hipLaunchKernelGGL((weno_flist3d_kernel<O, S, H, W>), dim3(1024), dim3(128), 0, L.stream, a, L.g, L.ph)
+  if (w0 && sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FL(SPLIT_LLF, HYB_PER_FIELD, W_L2IS);
+  else if (w0 && sp == SPLIT_ROE && hy == HYB_PER_FIELD) WL2_FL(SPLIT_ROE, HYB_PER_FIELD, W_L2IS);
+  else WL2_FL(-1, -1, -1);
 #undef WL2_FL
   hipLaunchKernelGGL((weno_sumlist3d_kernel<O>), dim3(1024), dim3(256), 0, L.stream, a, L.g, L.ph);
   return hipGetLastError();
 }
 
+// The correction kernels have builds for the weighting of Eq.(28) fixed at
+// compile time; the comparison weightings take builds that read it at run
+// time.  (A run-time choice keeps the values of all three in registers: the
+// every-face-WENO face kernel then needs more than 256 VGPRs and runs one
+// wave per SIMD, 1.6 against 1.2 ms per launch at 256^3.)
 hipError_t fused3d_fix(const FusedLaunch& L) {
   const FusedArgs a = make_args(L);
   const dim3 fg(1024), fb(128);
   const int sp = L.ph.split, hy = L.ph.hybrid;
-  if (L.fo3 != nullptr && sp == SPLIT_LLF && hy == HYB_WENO_ONLY)
-    return L.out_kind == OUT_RK ? fix_face_once<OUT_RK>(L, a) : fix_face_once<OUT_WRITE>(L, a);
+  const bool w0 = L.ph.weights == W_L2IS;
+  if (L.fo3 != nullptr && sp == SPLIT_LLF && hy == HYB_WENO_ONLY) {
+    if (L.out_kind == OUT_RK) return w0 ? fix_face_once<OUT_RK, W_L2IS>(L, a) : fix_face_once<OUT_RK, -1>(L, a);
+    return w0 ? fix_face_once<OUT_WRITE, W_L2IS>(L, a) : fix_face_once<OUT_WRITE, -1>(L, a);
+  }
   if (L.fo3 != nullptr && L.flist != nullptr && hy != HYB_WENO_ONLY)
     return L.out_kind == OUT_RK ? fix_face_lists<OUT_RK>(L, a) : fix_face_lists<OUT_WRITE>(L, a);
   if (!(sp == SPLIT_LLF && hy == HYB_WENO_ONLY)) {
@@ -144,14 +151,17 @@ hipError_t fused3d_fix(const FusedLaunch& L) {
     if (nreg > SCAN_LDS)
       hipLaunchKernelGGL(list_scan_kernel, dim3(1), dim3(1024), 0, L.stream, a.counts, nreg, a.offs);
   }
-#define WL2_FIX(O, S, H) \
-  hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H>), fg, fb, 0, L.stream, a, L.g, L.ph)
-#define WL2_FIX_SCHEMES(O)                                                           \
-  do {                                                                               \
-    if (sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_LLF, HYB_PER_FIELD); \
-    else if (sp == SPLIT_LLF && hy == HYB_WENO_ONLY) WL2_FIX(O, SPLIT_LLF, HYB_WENO_ONLY); \
-    else if (sp == SPLIT_ROE && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_ROE, HYB_PER_FIELD); \
-    else WL2_FIX(O, -1, -1);                                                         \
+#define WL2_FIX(O, S, H, W) \
+  hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H, W>), fg, fb, 0, L.stream, a, L.g, L.ph)
+  // every face WENO with LLF splitting has its own build for any weighting:
+  // the stage kernel's build for it lists no cell, and this build walks all
+#define WL2_FIX_SCHEMES(O)                                                                  \
+  do {                                                                                      \
+    if (w0 && sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_LLF, HYB_PER_FIELD, W_L2IS); \
+    else if (w0 && sp == SPLIT_LLF && hy == HYB_WENO_ONLY) WL2_FIX(O, SPLIT_LLF, HYB_WENO_ONLY, W_L2IS); \
+    else if (sp == SPLIT_LLF && hy == HYB_WENO_ONLY) WL2_FIX(O, SPLIT_LLF, HYB_WENO_ONLY, -1);  \
+    else if (w0 && sp == SPLIT_ROE && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_ROE, HYB_PER_FIELD, W_L2IS); \
+    else WL2_FIX(O, -1, -1, -1);                                                            \
   } while (0)
   if (L.out_kind == OUT_RK) WL2_FIX_SCHEMES(OUT_RK);
   else WL2_FIX_SCHEMES(OUT_WRITE);

@@ -267,27 +267,24 @@ __device__ __forceinline__ double weno_l2is_lr(double fm2, double fm1, double f0
   const double t2 = (fp2 - fm2) - 2.0 * (fp1 - fm1);
   const double tau5 = (13.0 / 12.0) * t1 * t1 + 0.25 * t2 * t2;
   const double e = fm1 - 2.0 * f0 + fp1;
-  double a0, a1, a2, a3;
-  if (wts == W_L2IS) {
-    const double E01 = e * e * (1.0 / 45.0);
-    const double lt = lam * tau5;
-    a0 = 0.4 * (1.0 + lt * fast_rcp(lam * b0 + E01 + eps_w));
-    a1 = 0.2 * (1.0 + lt * fast_rcp(lam * b1 + E01 + eps_w));
-    a2 = 0.3 * (1.0 + lt * fast_rcp(lam * b2 + eps_w));
-    a3 = 0.1 * (1.0 + lt * fast_rcp(lam * b3 + eps_w));
-  } else {
-    double r0 = tau5 * fast_rcp(b0 + eps_w), r1 = tau5 * fast_rcp(b1 + eps_w);
-    if (wts == W_IS_B01) {
-      const double g = fm1 - fp1;
-      const double r01 = tau5 * fast_rcp((13.0 / 12.0) * e * e + 0.25 * g * g + eps_w);
-      r0 *= r01;
-      r1 *= r01;
-    }
-    a0 = 0.4 * (1.0 + r0);
-    a1 = 0.2 * (1.0 + r1);
-    a2 = 0.3 * (1.0 + tau5 * fast_rcp(b2 + eps_w));
-    a3 = 0.1 * (1.0 + tau5 * fast_rcp(b3 + eps_w));
+  // one formula for the three weightings, the differences as selected
+  // factors (no branch: both would hold their values in registers):
+  // Eq.(28) d_k (1 + lam tau5 / (lam beta_k + E_k + eps)); Eq.(8) with lam
+  // = 1 and E_k = 0; Eq.(14) with the numerator of the two-point stencils
+  // multiplied by tau5 / (beta_01 + eps) of Eq.(15)
+  const bool l2 = wts == W_L2IS;
+  const double lv = l2 ? lam : 1.0;
+  const double E01 = l2 ? e * e * (1.0 / 45.0) : 0.0;
+  const double lt = lv * tau5;
+  double n01 = lt;
+  if (wts == W_IS_B01) {
+    const double g = fm1 - fp1;
+    n01 = tau5 * (tau5 * fast_rcp((13.0 / 12.0) * e * e + 0.25 * g * g + eps_w));
   }
+  const double a0 = 0.4 * (1.0 + n01 * fast_rcp(lv * b0 + E01 + eps_w));
+  const double a1 = 0.2 * (1.0 + n01 * fast_rcp(lv * b1 + E01 + eps_w));
+  const double a2 = 0.3 * (1.0 + lt * fast_rcp(lv * b2 + eps_w));
+  const double a3 = 0.1 * (1.0 + lt * fast_rcp(lv * b3 + eps_w));
   return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * fast_rcp((a0 + a1) + (a2 + a3));
 }
 
@@ -296,7 +293,8 @@ __device__ __forceinline__ double weno_l2is_lr(double fm2, double fm1, double f0
 // stencil cells are projected (Eq.(20)), split (Eq.(21)) and reconstructed
 // (Eq.(22)-(23)); the change with respect to the linear flux of that field is
 // back-projected (Eq.(24)).  Only one row and twelve split values are live.
-template <int NV, int DIR, int K, class Src>
+// W: the weighting (W_*) fixed at compile time, or -1 to read ph.weights.
+template <int NV, int DIR, int K, int W, class Src>
 __device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, double al, double dvk,
                                              double LFk, const KPhys& ph) {
   double r[NV];
@@ -315,19 +313,20 @@ __device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, d
   }
   const double t = dvk * s.irho;
   const double lam = ph.c_reg * (t * t);  // Eq.(32)
-  const double fw = weno_l2is_lr(fp[0], fp[1], fp[2], fp[3], fp[4], lam, ph.eps_w, ph.weights) +
-                    weno_l2is_lr(fm[5], fm[4], fm[3], fm[2], fm[1], lam, ph.eps_w, ph.weights);
+  const int wts = W >= 0 ? W : ph.weights;
+  const double fw = weno_l2is_lr(fp[0], fp[1], fp[2], fp[3], fp[4], lam, ph.eps_w, wts) +
+                    weno_l2is_lr(fm[5], fm[4], fm[3], fm[2], fm[1], lam, ph.eps_w, wts);
   return fw - (LFk + al * dvk);
 }
 
-template <int NV, int DIR, class Src>
+template <int NV, int DIR, int W = -1, class Src>
 __device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, const FaceState<NV>& st,
                                                 const KPhys& ph, double (&dF)[NV]) {
   double LF[NV], del[NV];
   project<NV, DIR>(st.s, st.Fc6, LF);
 #define WL2_LF(K)                                                                            \
   if constexpr (K < NV) {                                                                    \
-    del[K] = ((mask >> K) & 1u) ? lean_field<NV, DIR, K>(src, st.s, st.a[K], st.dv[K], LF[K], ph) \
+    del[K] = ((mask >> K) & 1u) ? lean_field<NV, DIR, K, W>(src, st.s, st.a[K], st.dv[K], LF[K], ph) \
                                 : 0.0;                                                       \
   }
   WL2_LF(0) WL2_LF(1) WL2_LF(2) WL2_LF(3) WL2_LF(4)
@@ -338,7 +337,7 @@ __device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, c
 // Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
 // the face below the cell, side 1 the face above.  Returns the change of the
 // face flux (WENO minus linear, Eq.(33) per field).
-template <int NV, int DIR, int SPLIT, int HYB>
+template <int NV, int DIR, int SPLIT, int HYB, int W = -1>
 __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, const KPhys& ph,
                                            const unsigned long long* lfb, int x, int y, int z,
                                            int side, double (&dF)[NV]) {
@@ -372,7 +371,7 @@ __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, cons
   FaceState<NV> st;
   const unsigned mask = face_linear_st<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin, st);
   if (mask) {
-    lean_correction<NV, DIR>(src, mask, st, ph, dF);
+    lean_correction<NV, DIR, W>(src, mask, st, ph, dF);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) dF[v] = 0.0;
@@ -382,7 +381,7 @@ __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, cons
 // Nonlinear correction of one listed cell by one lane: the flagged faces in
 // the fixed order x-, x+, y-, y+, z-, z+, +dF for the face below the cell and
 // -dF for the face above.
-template <int NV, int SPLIT, int HYB>
+template <int NV, int SPLIT, int HYB, int W = -1>
 __device__ __forceinline__ void serial_correction(const double* U, const KGrid& g,
                                                   const KPhys& ph, const StepCtl* ctl, int x,
                                                   int y, int z, unsigned cm, double (&acc)[NV]) {
@@ -396,13 +395,13 @@ __device__ __forceinline__ void serial_correction(const double* U, const KGrid& 
 #pragma unroll
     for (int v = 0; v < NV; ++v) dF[v] = 0.0;
     if (dir == 0) {
-      face_delta<NV, 0, SPLIT, HYB>(U, g, ph, ctl->lf_bits[0], x, y, z, side, dF);
+      face_delta<NV, 0, SPLIT, HYB, W>(U, g, ph, ctl->lf_bits[0], x, y, z, side, dF);
     } else if (dir == 1) {
       if constexpr (NV >= 4)
-        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[1], x, y, z, side, dF);
+        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB, W>(U, g, ph, ctl->lf_bits[1], x, y, z, side, dF);
     } else {
       if constexpr (NV >= 5)
-        face_delta<NV, (NV >= 5 ? 2 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[2], x, y, z, side, dF);
+        face_delta<NV, (NV >= 5 ? 2 : 0), SPLIT, HYB, W>(U, g, ph, ctl->lf_bits[2], x, y, z, side, dF);
     }
     const double sg = side ? -1.0 : 1.0;
 #pragma unroll
@@ -424,7 +423,7 @@ constexpr unsigned long long FIX_GROUPED_LANES = 64ull * 1024ull;
 // cell adds, the face above subtracts): the same bits as serial_correction,
 // with one face of latency instead of six (for short lists; a long list
 // keeps every lane busy with one cell each).
-template <int NV, int GRP, int SPLIT, int HYB>
+template <int NV, int GRP, int SPLIT, int HYB, int W = -1>
 __device__ __forceinline__ void grouped_correction(const double* U, const KGrid& g,
                                                    const KPhys& ph, const StepCtl* ctl, int x,
                                                    int y, int z, unsigned cm, double (&acc)[NV]) {
@@ -439,13 +438,13 @@ __device__ __forceinline__ void grouped_correction(const double* U, const KGrid&
   if (f < NF && ((cm >> f) & 1u)) {
     const int dir = f >> 1, side = f & 1;
     if (dir == 0) {
-      face_delta<NV, 0, SPLIT, HYB>(U, g, ph, ctl->lf_bits[0], x, y, z, side, dF);
+      face_delta<NV, 0, SPLIT, HYB, W>(U, g, ph, ctl->lf_bits[0], x, y, z, side, dF);
     } else if (dir == 1) {
       if constexpr (NV >= 4)
-        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[1], x, y, z, side, dF);
+        face_delta<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB, W>(U, g, ph, ctl->lf_bits[1], x, y, z, side, dF);
     } else {
       if constexpr (NV >= 5)
-        face_delta<NV, (NV >= 5 ? 2 : 0), SPLIT, HYB>(U, g, ph, ctl->lf_bits[2], x, y, z, side, dF);
+        face_delta<NV, (NV >= 5 ? 2 : 0), SPLIT, HYB, W>(U, g, ph, ctl->lf_bits[2], x, y, z, side, dF);
     }
   }
 #pragma unroll
