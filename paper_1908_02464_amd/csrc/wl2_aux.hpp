@@ -131,17 +131,14 @@ struct YGhostRule {
 }
 
 // Global LF speeds along every active direction: max over cells of
-// |u_d - c|, |u_d|, |u_d + c| (fields u-c, entropy/shear, u+c).
-[[maybe_unused]] static __global__ void lf_reset_kernel(StepCtl* ctl) {
-  if (threadIdx.x < 15) (&ctl->lf_bits[0][0])[threadIdx.x] = 0ull;
-}
-
+// |u_d - c|, |u_d|, |u_d + c| (fields u-c, entropy/shear, u+c), folded into
+// the block's slot of ctl->lf_slots (a NaN is raised to +inf, so it wins).
 template <int NV>
 __global__ __launch_bounds__(RED_BLOCK) void lf_reduce_kernel(const double* __restrict__ U,
                                                               long long ncell, double gamma,
                                                               StepCtl* ctl) {
   constexpr int DIM = NV - 2;
-  __shared__ double sh[RED_BLOCK / 64];
+  __shared__ double sh[RED_BLOCK / 64][3 * DIM];
   double mx[DIM][3];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) mx[d][0] = mx[d][1] = mx[d][2] = 0.0;
@@ -164,19 +161,45 @@ __global__ __launch_bounds__(RED_BLOCK) void lf_reduce_kernel(const double* __re
       mx[d][2] = fmax(mx[d][2], fabs(vel[d] + cs));
     }
   }
+  // the 3 DIM block maxima in one exchange through LDS
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double bm = block_max(mx[d][j], sh);
-      if (threadIdx.x == 0) {
-        const unsigned long long b = (unsigned long long)__double_as_longlong(bm);
-        if (j == 0) atomicMax(&ctl->lf_bits[d][0], b);
-        if (j == 2) atomicMax(&ctl->lf_bits[d][NV - 1], b);
-        if (j == 1)
-          for (int k = 1; k < NV - 1; ++k) atomicMax(&ctl->lf_bits[d][k], b);
-      }
+      const double v = mx[d][j];
+      const double w = wave_max(v != v ? __longlong_as_double(0x7ff0000000000000LL) : v);
+      if (lane == 0) sh[wid][3 * d + j] = w;
     }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 3 * DIM) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < RED_BLOCK / 64; ++i) r = fmax(r, sh[i][t]);
+    atomicMax(&ctl->lf_slots[blockIdx.x % LF_SLOTS].bits[t / 3][t % 3],
+              (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// The maximum over the slots into lf_bits (|u - c| for field 0, |u| for the
+// entropy and shear fields, |u + c| for field nv - 1; directions beyond the
+// grid's get 0) and the slots cleared for the next reduction.  One wave.
+[[maybe_unused]] static __global__ void lf_finalize_kernel(StepCtl* ctl, int nv) {
+  const int t = threadIdx.x;
+  if (t < 9) {
+    const int d = t / 3, j = t % 3;
+    unsigned long long m = 0ull;
+    for (int s = 0; s < LF_SLOTS; ++s) {
+      const unsigned long long b = ctl->lf_slots[s].bits[d][j];
+      m = b > m ? b : m;
+      ctl->lf_slots[s].bits[d][j] = 0ull;
+    }
+    if (j == 0) ctl->lf_bits[d][0] = m;
+    else if (j == 2) ctl->lf_bits[d][nv - 1] = m;
+    else
+      for (int k = 1; k < nv - 1; ++k) ctl->lf_bits[d][k] = m;
   }
 }
 

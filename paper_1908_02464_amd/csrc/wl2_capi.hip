@@ -217,14 +217,17 @@ hipError_t launch_cfl(const weno_l2is_ctx* c, const double* U, double dt_fixed, 
   return hipGetLastError();
 }
 
+// Global LF speeds of U: per-block maxima into the slots, then the maximum
+// over the slots into ctl->lf_bits (the slots are zero between reductions:
+// the control block starts zeroed and the finalize kernel clears them).
 hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
-  hipLaunchKernelGGL(lf_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl);
   const unsigned b = red_blocks(c->ncell);
   switch (c->nvar) {
     case 3: hipLaunchKernelGGL(lf_reduce_kernel<3>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
     case 4: hipLaunchKernelGGL(lf_reduce_kernel<4>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
     default: hipLaunchKernelGGL(lf_reduce_kernel<5>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
   }
+  hipLaunchKernelGGL(lf_finalize_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, c->nvar);
   return hipGetLastError();
 }
 
@@ -299,7 +302,10 @@ hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, do
   L.rk_b = rb;
   L.out_kind = out_kind;
   L.ych = row_ych(c);
-  L.fast = c->p.split == WL2_SPLIT_LLF && c->p.hybrid == WL2_HYB_PER_FIELD;
+  L.fast = c->p.hybrid != WL2_HYB_PER_FIELD ? 0
+           : c->p.split == WL2_SPLIT_LLF   ? 1
+           : c->p.split == WL2_SPLIT_LF    ? 2
+                                           : 0;
   L.nvar = c->nvar;
   L.list = c->list;
   L.list_n = turn.cur;

@@ -71,6 +71,16 @@ struct alignas(128) CflSlot {
   unsigned long long bits;
 };
 
+// Global Lax-Friedrichs speeds: the blocks of the reduction fold their
+// maxima into LF_SLOTS slots (block b into slot b mod LF_SLOTS), each in its
+// own 128-byte line, so that their atomics do not queue on one address (on
+// one line, 2048 blocks x 8 atomics took 34 us at 1024^2); a one-wave kernel
+// then takes the maximum over the slots into lf_bits and clears them.
+constexpr int LF_SLOTS = 16;
+struct alignas(128) LfSlot {
+  unsigned long long bits[3][3];  // direction, (|u - c|, |u|, |u + c|) maxima (raw bits)
+};
+
 // Device control block of one grid (time step, clock, status).
 struct StepCtl {
   unsigned int status;           // sticky: bit 0 = non-physical state seen
@@ -84,6 +94,7 @@ struct StepCtl {
                                  // stages alternate between the two counters, and each
                                  // stage's correction kernel clears the next one's
   CflSlot smax[CFL_SLOTS];       // running CFL maximum, spread over slots
+  LfSlot lf_slots[LF_SLOTS];     // global LF speeds being reduced (zero between reductions)
 };
 
 // Fold a maximum (> 0, or +inf standing for NaN) into the wave's slot.

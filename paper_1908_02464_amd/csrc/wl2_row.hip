@@ -10,10 +10,16 @@ static_assert(ROW_TILE == RT, "one tile width for host and device");
 
 namespace {
 
+// Builds: LLF or global-LF splitting with the per-field switch fixed at
+// compile time (the paper's 1D and 2D choices), any other scheme read at
+// run time (those builds spill; at 1024^2 global LF took 0.26 ms per step
+// through them against 0.19 for the LLF build).
 template <int NV, int OUT>
 void launch_nv(const RowLaunch& L, const RowArgs& a, dim3 grid, int ych, int tiles_x) {
-  if (L.fast)
-    hipLaunchKernelGGL((row_kernel<NV, OUT, 0, 0>), grid, dim3(RW), 0, L.stream, a, L.g, L.ph, ych, tiles_x);
+  if (L.fast == 1)
+    hipLaunchKernelGGL((row_kernel<NV, OUT, SPLIT_LLF, HYB_PER_FIELD>), grid, dim3(RW), 0, L.stream, a, L.g, L.ph, ych, tiles_x);
+  else if (L.fast == 2)
+    hipLaunchKernelGGL((row_kernel<NV, OUT, SPLIT_LF, HYB_PER_FIELD>), grid, dim3(RW), 0, L.stream, a, L.g, L.ph, ych, tiles_x);
   else
     hipLaunchKernelGGL((row_kernel<NV, OUT, -1, -1>), grid, dim3(RW), 0, L.stream, a, L.g, L.ph, ych, tiles_x);
 }
@@ -33,8 +39,8 @@ hipError_t row1d_steps(double* U, double* U1, double* U2, StepCtl* ctl, unsigned
   constexpr int W = 8;
   if (g.n[1] != 1 || g.n[2] != 1 || g.n[0] > ROW_STEPS_MAX_CELLS) return hipErrorInvalidValue;
   const RowStepsArgs s{U, U1, U2, ctl, list, cfl_dx, n_steps};
-  if (fast)
-    hipLaunchKernelGGL((row1d_steps_kernel<W, 0, 0>), dim3(1), dim3(W * RW), 0, stream, s, g, ph);
+  if (fast == 1)
+    hipLaunchKernelGGL((row1d_steps_kernel<W, SPLIT_LLF, HYB_PER_FIELD>), dim3(1), dim3(W * RW), 0, stream, s, g, ph);
   else
     hipLaunchKernelGGL((row1d_steps_kernel<W, -1, -1>), dim3(1), dim3(W * RW), 0, stream, s, g, ph);
   return hipGetLastError();
@@ -55,17 +61,23 @@ hipError_t row_fix(const RowLaunch& L) {
                        L.fo_map, L.fo_cap);                                                      \
   } while (0)
     if (L.out_kind == OUT_RK) {
-      if (L.fast) WL2_FO(OUT_RK, 0, 0); else WL2_FO(OUT_RK, -1, -1);
+      if (L.fast == 1) WL2_FO(OUT_RK, SPLIT_LLF, HYB_PER_FIELD);
+      else if (L.fast == 2) WL2_FO(OUT_RK, SPLIT_LF, HYB_PER_FIELD);
+      else WL2_FO(OUT_RK, -1, -1);
     } else {
-      if (L.fast) WL2_FO(OUT_WRITE, 0, 0); else WL2_FO(OUT_WRITE, -1, -1);
+      if (L.fast == 1) WL2_FO(OUT_WRITE, SPLIT_LLF, HYB_PER_FIELD);
+      else if (L.fast == 2) WL2_FO(OUT_WRITE, SPLIT_LF, HYB_PER_FIELD);
+      else WL2_FO(OUT_WRITE, -1, -1);
     }
 #undef WL2_FO
     return hipGetLastError();
   }
 #define WL2_FIX(NV, O)                                                                     \
   do {                                                                                     \
-    if (L.fast)                                                                            \
-      hipLaunchKernelGGL((row_fix_kernel<NV, O, 0, 0>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+    if (L.fast == 1)                                                                       \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, SPLIT_LLF, HYB_PER_FIELD>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+    else if (L.fast == 2)                                                                  \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, SPLIT_LF, HYB_PER_FIELD>), fg, fb, 0, L.stream, a, L.g, L.ph); \
     else                                                                                   \
       hipLaunchKernelGGL((row_fix_kernel<NV, O, -1, -1>), fg, fb, 0, L.stream, a, L.g, L.ph); \
   } while (0)

@@ -17,7 +17,9 @@ struct RowLaunch {
   double rk_a, rk_b;
   int out_kind;  // OUT_WRITE or OUT_RK
   int ych;       // rows per work item (2D)
-  int fast;      // LLF splitting with the per-field switch (compile-time path)
+  int fast;      // compile-time build with the per-field switch: 1 = LLF
+                 // splitting, 2 = global LF splitting, 0 = the scheme read at
+                 // run time
   int nvar;      // 3 (1D) or 4 (2D)
   unsigned long long* list;  // correction list (ncell entries) and its length
   unsigned int* list_n;

@@ -121,7 +121,8 @@ def double_mach(nx=512, ny=128, gamma=GAMMA):
     bottom a wall from x = 0.1667 on and the post-shock state left of it;
     the top the exact position of the moving shock, x = 0.1667 + (y + 20 t)
     / 1.732 (the shock moves at 10 normal to itself into gas with sound speed
-    1), post-shock left of it and pre-shock right of it."""
+    1), post-shock left of it and pre-shock right of it; global LF splitting
+    (the paper's splitting for its 2D cases)."""
     assert nx == 4 * ny
     x, dx = centres(nx, 0.0, 4.0)
     y, _ = centres(ny, 0.0, 1.0)
@@ -134,7 +135,7 @@ def double_mach(nx=512, ny=128, gamma=GAMMA):
     pre_s = conserved(np.array(DMR_PRE[0]), [np.array(DMR_PRE[1]), np.array(DMR_PRE[2])],
                       np.array(DMR_PRE[3]), gamma).ravel()
     inflow = np.ascontiguousarray(np.repeat(post.reshape(4, 1), ny, axis=1))
-    params = {"bc": [3, 1, 4, 5, 1, 1],
+    params = {"bc": [3, 1, 4, 5, 1, 1], "split": 1,
               "bstate": [list(post) + [0.0], list(pre_s) + [0.0]],
               # wall from x = 0.1667; front x0, dx/dy, dx/dt
               "bgeom": [DMR_X0, DMR_X0, 1.0 / DMR_SLOPE, 20.0 / DMR_SLOPE]}

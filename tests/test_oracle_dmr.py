@@ -56,7 +56,9 @@ def test_state_sides_equal_a_grid_extended_by_their_ghost_rows(orc):
     elsewhere; above, post- or pre-shock by the front's position at each
     ghost centre at time t."""
     nx, ny = 128, 32
-    U, dx, prm, inf = _dmr(nx, ny)
+    # LLF splitting: global LF speeds would also take the extended grid's
+    # ghost rows, which are interior cells there
+    U, dx, prm, inf = _dmr(nx, ny, split=0)
     p0 = orc.params(nx, ny, 1, dx, inflow=inf, **prm)
     t = 0.013
     orc.run(U, dx, G, p0, t)
