@@ -593,22 +593,26 @@ def _sample_cells(shape, n, rng):
     return np.unique(np.array(cells, dtype=np.int64))
 
 
-@pytest.mark.parametrize("which", ["quad1024", "turb256"])
+@pytest.mark.parametrize("which", ["quad1024", "quad1024_lf", "turb256", "turb256_lf"])
 def test_full_size_sampled(orc, capi, which):
     """Bench-size workloads: device dt equals the oracle's CFL dt exactly; dU/dt
     at sampled cells; and one full SSP-RK3 step (the launch sequence the
-    benchmark times) at sampled cells via an oracle step on a sub-box."""
+    benchmark times) at sampled cells via an oracle step on a sub-box.  With
+    global LF splitting (the grid-wide speed reduction over 2048 blocks and
+    its slots, the compile-time LF row builds) the right-hand side only: an
+    oracle step on a sub-box would take the sub-box's own LF speeds."""
     import torch
     say(f"[full] {which}")
     rng = np.random.default_rng(1)
-    if which == "quad1024":
+    if which.startswith("quad1024"):
         U, dx, _ = w.four_quadrant_2d(1024, 1024, 2024)
         bc = [1] * 6
     else:
         U, dx = w.turbulence_3d(256, 2024)
         bc = [0] * 6
+    lf = which.endswith("_lf")
     shape = shape_of(U)
-    po, pg = params_pair(orc, capi, shape, dx, bc=bc)
+    po, pg = params_pair(orc, capi, shape, dx, bc=bc, **({"split": 1} if lf else {}))
     ctx = capi.Context(*shape, dx, G, pg)
     Ud = to_dev(U)
     dt_g, st = ctx.cfl_dt(Ud)
@@ -626,6 +630,9 @@ def test_full_size_sampled(orc, capi, which):
     say(f"    rhs sampled cells={cells.size} err(state units)={err:.3e}")
     assert err <= 1e-12
     del out
+    if lf:
+        ctx.close()
+        return
     # one full step with the device CFL dt
     ctx.step(Ud)
     _, dt_used = ctx.time()
