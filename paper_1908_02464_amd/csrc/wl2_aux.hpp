@@ -132,7 +132,9 @@ struct YGhostRule {
 
 // Global LF speeds along every active direction: max over cells of
 // |u_d - c|, |u_d|, |u_d + c| (fields u-c, entropy/shear, u+c), folded into
-// the block's slot of ctl->lf_slots (a NaN is raised to +inf, so it wins).
+// the block's slot of ctl->lf_slots.  fmax passes over a NaN speed, as the
+// oracle's comparison does (a non-physical cell stops the run through the
+// CFL status instead).
 template <int NV>
 __global__ __launch_bounds__(RED_BLOCK) void lf_reduce_kernel(const double* __restrict__ U,
                                                               long long ncell, double gamma,
@@ -167,8 +169,7 @@ __global__ __launch_bounds__(RED_BLOCK) void lf_reduce_kernel(const double* __re
   for (int d = 0; d < DIM; ++d) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double v = mx[d][j];
-      const double w = wave_max(v != v ? __longlong_as_double(0x7ff0000000000000LL) : v);
+      const double w = wave_max(mx[d][j]);
       if (lane == 0) sh[wid][3 * d + j] = w;
     }
   }
