@@ -79,10 +79,11 @@ __global__ __launch_bounds__(RW, 2) void batch_row_kernel(const BGrid* __restric
     const StageRefs sr = stage_refs(G, stage);
     const RowArgs a{sr.Uk, sr.out, G.U, G.ctl, sr.ra, sr.rb, list, list_n,
                     (unsigned long long)it.slot << 40, nullptr, nullptr};
+    // (a batch admits no grid with state sides: their checks compiled out)
     if (G.ph.split == SPLIT_LLF && G.ph.hybrid == HYB_PER_FIELD)
-      row_item<NV, OUT_RK, 0, 0>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
+      row_item<NV, OUT_RK, 0, 0, false>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
     else
-      row_item<NV, OUT_RK, -1, -1>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
+      row_item<NV, OUT_RK, -1, -1, false>(a, G.g, G.ph, buf, ring, it.x0, it.y0, it.y1, dt);
   }
 }
 

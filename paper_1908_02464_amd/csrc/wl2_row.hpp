@@ -118,7 +118,7 @@ struct Win6Src {  // six records in registers
 
 // Raw cell (column element offset xy, row y) of a 2D grid, ghost-mapped in
 // y; the mirror flip of the y momentum is reported, not applied.
-template <int NV>
+template <int NV, bool YS = true>
 __device__ __forceinline__ void row_load_raw(const double* __restrict__ U, const KGrid& g,
                                              long long xy, int y, double (&u)[NV]) {
   bool fy = false;
@@ -126,8 +126,9 @@ __device__ __forceinline__ void row_load_raw(const double* __restrict__ U, const
   const long long off = xy + (long long)iy * g.stride[1];
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = U[v * g.ncell + off];
-  // state ghosts of a y side (2D grids: xy is the column's x)
-  if (NV == 4 && (y < 0 || y >= g.n[1]) && is_yghost(g, y)) load_yghost<NV>(g, xy, y, u);
+  // state ghosts of a y side (2D grids: xy is the column's x; YS false: the
+  // caller's grids have none, and the check is compiled out)
+  if (YS && NV == 4 && (y < 0 || y >= g.n[1]) && is_yghost(g, y)) load_yghost<NV>(g, xy, y, u);
 }
 
 template <int NV>
@@ -143,7 +144,7 @@ __device__ __forceinline__ void row_flip(const KGrid& g, bool fx, int y, double 
 // and the stage combination; cells next to a flagged face are listed.
 // Called by whole wavefronts; `buf` is the item's LDS row buffer [NV+3][RB],
 // `ring` its window ring [2][NV+3][RW] (2D).
-template <int NV, int OUT, int SPLIT, int HYB>
+template <int NV, int OUT, int SPLIT, int HYB, bool YS = true>
 __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const KPhys& ph,
                                          double (*buf)[RB], double (*ring)[NV + 3][RW], int x0,
                                          int y0, int y1, double dt) {
@@ -171,14 +172,14 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
   if constexpr (NV == 3) {
     // 1D: one row
     double u[NV];
-    row_load_raw<NV>(a.Uk, g, oxy, 0, u);
+    row_load_raw<NV, YS>(a.Uk, g, oxy, 0, u);
     row_flip<NV>(g, fx, 0, u);
     LRec<NV> own_rec;
     make_lrec<NV>(u, ph, own_rec);
     row_put<NV>(buf, lane + 3, own_rec);
     if (halo) {
       double hu[NV];
-      row_load_raw<NV>(a.Uk, g, hxy, 0, hu);
+      row_load_raw<NV, YS>(a.Uk, g, hxy, 0, hu);
       row_flip<NV>(g, fxh, 0, hu);
       if (hin) load_inflow<NV>(g, 0, hu);
       LRec<NV> hr;
@@ -230,25 +231,25 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
     {
       LRec<NV> cm3, cm2, cm1;
       double u[NV];
-      row_load_raw<NV>(a.Uk, g, oxy, y0 - 3, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 - 3, u);
       row_flip<NV>(g, fx, y0 - 3, u);
       make_lrec<NV>(u, ph, cm3);
-      row_load_raw<NV>(a.Uk, g, oxy, y0 - 2, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 - 2, u);
       row_flip<NV>(g, fx, y0 - 2, u);
       make_lrec<NV>(u, ph, cm2);
-      row_load_raw<NV>(a.Uk, g, oxy, y0 - 1, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 - 1, u);
       row_flip<NV>(g, fx, y0 - 1, u);
       make_lrec<NV>(u, ph, cm1);
-      row_load_raw<NV>(a.Uk, g, oxy, y0, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0, u);
       row_flip<NV>(g, fx, y0, u);
       make_lrec<NV>(u, ph, r0);
-      row_load_raw<NV>(a.Uk, g, oxy, y0 + 1, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 + 1, u);
       row_flip<NV>(g, fx, y0 + 1, u);
       make_lrec<NV>(u, ph, r1);
-      row_load_raw<NV>(a.Uk, g, oxy, y0 + 2, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 + 2, u);
       row_flip<NV>(g, fx, y0 + 2, u);
       make_lrec<NV>(u, ph, r2);
-      row_load_raw<NV>(a.Uk, g, oxy, y0 + 3, u);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 + 3, u);
       row_flip<NV>(g, fx, y0 + 3, u);
       make_lrec<NV>(u, ph, r3);
       ring_put<NV>(ring, (y0 - 2) & 1, lane, cm2);
@@ -256,8 +257,8 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
       // face y0 - 1/2: cells y0-3 .. y0+2
       const LRec<NV> wp[6] = {cm3, cm2, cm1, r0, r1, r2};
       yprev = face_linear_l<NV, 1, SPLIT, HYB>(Win6Src<NV>{wp}, ph, ph.eps_thr[1], lfy, Fyp) != 0u;
-      row_load_raw<NV>(a.Uk, g, oxy, y0 + 4, upre);
-      if (halo) row_load_raw<NV>(a.Uk, g, hxy, y0, hpre);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y0 + 4, upre);
+      if (halo) row_load_raw<NV, YS>(a.Uk, g, hxy, y0, hpre);
     }
     for (int y = y0; y < y1; ++y) {
       row_put<NV>(buf, lane + 3, r0);  // cell (x, y)
@@ -268,7 +269,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
         make_lrec<NV>(hpre, ph, hr);
         row_put<NV>(buf, hslot, hr);
         asm volatile("" ::: "memory");  // the prefetch below stays after this use
-        row_load_raw<NV>(a.Uk, g, hxy, y + 1, hpre);
+        row_load_raw<NV, YS>(a.Uk, g, hxy, y + 1, hpre);
       }
       __syncthreads();
       __builtin_amdgcn_s_setprio(0);
@@ -328,7 +329,7 @@ __device__ __forceinline__ void row_item(const RowArgs& a, const KGrid& g, const
       make_lrec<NV>(upre, ph, r3);
       asm volatile("" ::"v"(r3.U[0]), "v"(r3.U[NV - 1]), "v"(r3.p), "v"(r3.c), "v"(r3.iw)
                    : "memory");
-      row_load_raw<NV>(a.Uk, g, oxy, y + 5, upre);
+      row_load_raw<NV, YS>(a.Uk, g, oxy, y + 5, upre);
       __syncthreads();  // row buffer free for the next row
     }
   }
