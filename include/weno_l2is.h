@@ -118,7 +118,7 @@ int weno_l2is_params_default(weno_l2is_params *p, int nx, int ny, int nz,
 /* Create a solver context for one grid.  hip_stream: hipStream_t (NULL =
  * the null stream); all of the context's work is enqueued there.  Allocates
  * the two RK stage buffers, one accumulator (per-direction path), the
- * correction list (8 bytes per cell), a 4.4 KB control block, for 2D
+ * correction list (8 bytes per cell), a 6.4 KB control block, for 2D
  * grids of 131072 cells or more the face-once correction buffers (68 bytes
  * per cell), and for 3D grids a face buffer (120 bytes per cell) where the
  * corrections compute each face once: with every face WENO (LLF
@@ -154,7 +154,7 @@ int weno_l2is_rhs_release(void);
  * allocate (code under HIP graph capture, tight serving loops, harnesses
  * that forbid it).  The same dU/dt, bit for bit, enqueued on hip_stream
  * (hipStream_t; NULL = the null stream).  Its scratch (control block and
- * correction list: 8 bytes per cell plus 4.6 KB, and 8 bytes per column
+ * correction list: 8 bytes per cell plus 6.4 KB, and 8 bytes per column
  * tile and plane in 3D) lives in a static device array of
  * WL2_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, held until the
  * process ends; grids whose scratch does not fit (about 8.3M cells) are
@@ -162,7 +162,10 @@ int weno_l2is_rhs_release(void);
  * shares that GPU's array (the control block is cleared by a kernel at the
  * start of each call): calls that overlap on one GPU (different streams,
  * different threads) race, so the caller orders them.  No inflow or state
- * side (WL2_E_BC).  Other arguments and errors as weno_l2is_rhs. */
+ * side (WL2_E_BC).  Other arguments and errors as weno_l2is_rhs.  (The
+ * library allocates nothing here; the builds of some schemes keep spilled
+ * registers in private memory, which the HIP runtime reserves for a queue
+ * at the first launch of such a build on it, as for any kernel.) */
 int weno_l2is_rhs_noalloc(const double *U, int nx, int ny, int nz, double dx,
                           double gamma, const weno_l2is_params *params,
                           double *dUdt, void *hip_stream);

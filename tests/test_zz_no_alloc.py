@@ -43,6 +43,8 @@ def _pairs():
     return [
         ("1d", (s1[0], s1[1], [1] * 6, {}), (s2[0], s2[1], [1] * 6, {})),
         ("2d", (q1[0], q1[1], [1] * 6, {}), (q2[0], q2[1], [0, 0, 2, 2, 1, 1], {"hybrid": 1})),
+        # global LF: the speed reduction's slots live in the static scratch
+        ("2d_lf", (q1[0], q1[1], [1] * 6, {"split": 1}), (q2[0], q2[1], [1] * 6, {"split": 1})),
         ("3d", (t1[0], t1[1], [0] * 6, {}), (t2[0], t2[1], [0] * 6, {"split": 2})),
         ("3d_weno_only", (t1[0], t1[1], [0] * 6, {"hybrid": 2}), (t2[0], t2[1], [1, 1, 2, 2, 0, 0], {"split": 1})),
         ("2d_to_1d", (q1[0], q1[1], [1] * 6, {"weights": 2}), (s2[0], s2[1], [2, 2, 1, 1, 1, 1], {"hybrid": 2})),
@@ -77,8 +79,23 @@ def test_noalloc_rhs_equals_rhs(capi, name):
         d = float(np.abs(a - b).max())
         say(f"    max |noalloc - rhs| = {d:.3e}")
         assert np.array_equal(a, b)
-    # the second call allocated nothing on the device
-    assert free[3] == free[2], free
+    # Nothing allocated on the device: both calls once more, with free
+    # device memory read around them.  (The first launch of a build that
+    # keeps spilled registers in private memory makes the HIP runtime
+    # reserve that memory for the queue; the calls above have done so.)
+    args = []
+    for U, dx, bc, kw in pair[1:]:
+        shape = shape_of(U)
+        Ud = to_dev(U)
+        args.append((Ud, shape, dx, capi.params_default(*shape, dx, bc=bc, **kw), torch.empty_like(Ud)))
+    torch.cuda.synchronize()
+    before = torch.cuda.mem_get_info()[0]
+    for Ud, shape, dx, p, got in args:
+        capi.rhs_noalloc(Ud, *shape, dx, G, p, got, stream=stream)
+    stream.synchronize()
+    after = torch.cuda.mem_get_info()[0]
+    say(f"    free device memory before / after the repeated calls: {before} / {after}")
+    assert after == before, (before, after, free)
 
 
 def test_noalloc_rhs_refusals(capi):
