@@ -403,7 +403,7 @@ def main():
     # event-timed launch against the 8 TB/s peak (the unit the target is set
     # in), with the counted HBM traffic of the committed rocprofv3 summary
     # (same kernel-source hash, else null).  Beside it the FP64 side: the
-    # FP64 operations counted for this build over the same time, against the
+    # FP64 operations counted for this kernel binary over the same time, against the
     # FP64 vector peak; the counters count every lane of a wave instruction,
     # so lanes left idle by partial waves make it an upper bound.
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),

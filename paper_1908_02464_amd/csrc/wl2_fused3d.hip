@@ -154,7 +154,8 @@ hipError_t fused3d_fix(const FusedLaunch& L) {
 #define WL2_FIX(O, S, H, W) \
   hipLaunchKernelGGL((weno_fix3d_kernel<O, S, H, W>), fg, fb, 0, L.stream, a, L.g, L.ph)
   // every face WENO with LLF splitting has its own build for any weighting:
-  // the stage kernel's build for it lists no cell, and this build walks all
+  // the stage kernel's build for it lists no cell, and the correction
+  // kernel's build for it walks every cell
 #define WL2_FIX_SCHEMES(O)                                                                  \
   do {                                                                                      \
     if (w0 && sp == SPLIT_LLF && hy == HYB_PER_FIELD) WL2_FIX(O, SPLIT_LLF, HYB_PER_FIELD, W_L2IS); \
