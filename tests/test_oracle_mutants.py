@@ -12,7 +12,9 @@ weights of another WENO family (inverse-square smoothness weights), which
 lose the fifth order on smooth data, and three readings the paper leaves
 open: shear eigenvectors without the Roe sound speed, the LLF speed over
 the face's two cells instead of its six-cell stencil, and a time step from
-the fastest single direction instead of the sum over directions.
+the fastest single direction instead of the sum over directions; and slips
+in the comparison weightings, the moving boundary of the double Mach
+reflection and the global LF speeds.
 """
 import os
 import shutil
@@ -75,6 +77,10 @@ MUTANTS = [
     # row's centre instead of the ghost's)
     ("front_ghost_height", "solver.c",
      "yc = (k + 0.5) * g->dx;", "yc = (k - 0.5) * g->dx;"),
+    # global LF speeds of the two acoustic fields exchanged
+    ("lf_acoustic_fields_swapped", "solver.c",
+     "double e = fabs(s == 0 ? un - cs : (s == g->nvar - 1 ? un + cs : un));",
+     "double e = fabs(s == 0 ? un + cs : (s == g->nvar - 1 ? un - cs : un));"),
     # time step from the largest single-direction speed instead of the sum
     ("cfl_max_over_directions", "solver.c",
      "for (d = 0; d < g->dim; ++d) s += fabs(prim[1 + d]) + prim[5];\n    if (s > smax || s != s)",

@@ -261,6 +261,60 @@ def test_z6_llf_speed_is_the_six_cell_maximum(orc, nvar, d, hybrid):
                 assert np.abs(ref2 - ref6).max() > 1e3 * tol
 
 
+@pytest.mark.parametrize("shape", [(24, 1, 1), (12, 10, 1), (9, 8, 7)])
+@pytest.mark.parametrize("hybrid", [3, 2])
+def test_global_lf_speed_is_the_grid_maximum(orc, shape, hybrid):
+    """Global LF splitting (Eq.(21) with l over the whole domain): alpha^s
+    along d is the maximum over every cell of the grid of |u_d - c|, |u_d|,
+    |u_d + c|.  On a periodic grid of random states with one fast cell far
+    from the cell examined, dU/dt there equals the flux difference of the
+    upwind reconstructions with those grid maxima (every face linear, or
+    every face on the WENO branch with lambda = 0: the optimal weights), and
+    it changes when the fast cell is slowed down."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(600 + nx + 3 * ny + 5 * nz)
+    nvar = 2 + (1 + (ny > 1) + (nz > 1))
+    dim = nvar - 2
+    U = np.zeros((nvar, nz, ny, nx))
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                U[:, iz, iy, ix] = rand_state(rng, nvar, 0.5)
+    # a fast cell in a corner, out of every stencil of the centre cell
+    rho = U[0, 0, 0, 0]
+    vel = U[1:-1, 0, 0, 0] / rho
+    pr = (G - 1) * (U[-1, 0, 0, 0] - 0.5 * rho * vel @ vel)
+    vel[:] = 3.0
+    U[:, 0, 0, 0] = np.array([rho] + list(rho * vel) + [pr / (G - 1) + 0.5 * rho * vel @ vel])
+    dx = 0.1
+    kw = {"hybrid": hybrid, "split": 1, "bc": [0] * 6}
+    if hybrid == 2:
+        kw["c_reg"] = 0.0
+    p = orc.params(nx, ny, nz, dx, **kw)
+    c = np.array([nx // 2, ny // 2, nz // 2])
+    cell = c[0] + nx * (c[1] + ny * c[2])
+    flat = U.reshape(nvar, -1).T
+    ref = np.zeros(nvar)
+    for d in range(dim):
+        a = np.array([cell_speeds(u, nvar, d) for u in flat]).max(axis=0)
+        faces = []
+        for side in (0, 1):  # the face below the cell, then the one above
+            U6 = []
+            for m in range(6):
+                q = c.copy()
+                q[d] = (q[d] + side - 3 + m) % shape[d]
+                U6.append(U[:, q[2], q[1], q[0]])
+            faces.append(upwind_flux(orc, nvar, d, np.array(U6), a))
+        ref -= (faces[1] - faces[0]) / dx
+    got = orc.rhs_at(U, dx, G, p, [cell])[:, 0]
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    V = U.copy()
+    V[1:-1, 0, 0, 0] *= 0.1
+    V[-1, 0, 0, 0] = U[-1, 0, 0, 0] - 0.5 * (U[1:-1, 0, 0, 0] @ U[1:-1, 0, 0, 0]
+                                            - V[1:-1, 0, 0, 0] @ V[1:-1, 0, 0, 0]) / rho
+    assert np.abs(orc.rhs_at(V, dx, G, p, [cell])[:, 0] - got).max() > 1e-6 * np.abs(got).max()
+
+
 @pytest.mark.parametrize("shape,bc", [((40, 1, 1), [0, 0, 1, 1, 1, 1]),
                                       ((16, 14, 1), [0, 0, 0, 0, 1, 1]),
                                       ((12, 11, 10), [0] * 6)])
