@@ -77,6 +77,9 @@ MUTANTS = [
     # row's centre instead of the ghost's)
     ("front_ghost_height", "solver.c",
      "yc = (k + 0.5) * g->dx;", "yc = (k - 0.5) * g->dx;"),
+    # Roe splitting speeds taken in the reverse field order
+    ("roe_speed_field_order", "face.c",
+     "alpha[s] = fabs(lam[s]);", "alpha[s] = fabs(lam[nvar - 1 - s]);"),
     # global LF speeds of the two acoustic fields exchanged
     ("lf_acoustic_fields_swapped", "solver.c",
      "double e = fabs(s == 0 ? un - cs : (s == g->nvar - 1 ? un + cs : un));",

@@ -261,6 +261,48 @@ def test_z6_llf_speed_is_the_six_cell_maximum(orc, nvar, d, hybrid):
                 assert np.abs(ref2 - ref6).max() > 1e3 * tol
 
 
+def roe_eigenvalues(UL, UR, nvar, d):
+    """u_n - c~, u_n (nvar - 2 times), u_n + c~ at the Roe state of two
+    cells: velocity and total enthalpy averaged with sqrt(rho) weights,
+    c~^2 = (gamma - 1) (H~ - |u~|^2 / 2)."""
+    def prim(U):
+        rho = U[0]
+        vel = U[1:-1] / rho
+        p = (G - 1) * (U[-1] - 0.5 * rho * vel @ vel)
+        return rho, vel, (U[-1] + p) / rho
+    rl, vl, hl = prim(UL)
+    rr, vr, hr = prim(UR)
+    wl, wr = np.sqrt(rl), np.sqrt(rr)
+    v = (wl * vl + wr * vr) / (wl + wr)
+    h = (wl * hl + wr * hr) / (wl + wr)
+    c = np.sqrt((G - 1) * (h - 0.5 * v @ v))
+    return np.array([v[d] - c] + [v[d]] * (nvar - 2) + [v[d] + c])
+
+
+@pytest.mark.parametrize("nvar,d", CASES)
+@pytest.mark.parametrize("hybrid", [3, 2])
+def test_roe_splitting_speed_is_the_roe_eigenvalue(orc, nvar, d, hybrid):
+    """Roe splitting (Sec. 2.3 step (4)): alpha^s = |lambda^s| at the Roe
+    state of x_{j+1/2}, whatever the other stencil cells hold: the face flux
+    equals the upwind reconstruction with those speeds (every face linear, or
+    the WENO branch with lambda = 0), and differs from the one with the
+    six-cell maxima."""
+    rng = np.random.default_rng(700 + 7 * nvar + d)
+    kw = {"hybrid": hybrid, "split": 2}
+    if hybrid == 2:
+        kw["c_reg"] = 0.0
+    p = orc.params(8, 1, 1, 0.1, **kw)
+    for _ in range(8):
+        U6 = np.array([rand_state(rng, nvar, 0.8) for _ in range(6)])
+        a = np.abs(roe_eigenvalues(U6[2], U6[3], nvar, d))
+        F, _, _ = orc.face_flux(nvar, d, G, p, 1e-7, U6)
+        ref = upwind_flux(orc, nvar, d, U6, a)
+        tol = 1e-12 * (1 + np.abs(ref).max())
+        np.testing.assert_allclose(F, ref, rtol=0, atol=tol)
+        a6 = np.array([cell_speeds(u, nvar, d) for u in U6]).max(axis=0)
+        assert np.abs(upwind_flux(orc, nvar, d, U6, a6) - ref).max() > 1e3 * tol
+
+
 @pytest.mark.parametrize("shape", [(24, 1, 1), (12, 10, 1), (9, 8, 7)])
 @pytest.mark.parametrize("hybrid", [3, 2])
 def test_global_lf_speed_is_the_grid_maximum(orc, shape, hybrid):
