@@ -77,6 +77,19 @@ MUTANTS = [
     # row's centre instead of the ghost's)
     ("front_ghost_height", "solver.c",
      "yc = (k + 0.5) * g->dx;", "yc = (k - 0.5) * g->dx;"),
+    # lambda of Eq.(32) from sqrt(sigma) instead of sigma
+    ("lambda_sqrt_sigma", "face.c",
+     "lr = p->c_reg * sig[s];", "lr = p->c_reg * sqrt(sig[s]);"),
+    # the threshold of Eq.(35) with one power of dx/L too few
+    ("threshold_power", "solver.c",
+     "for (k = 0; k < p->thr_alpha; ++k) e *= r;", "for (k = 1; k < p->thr_alpha; ++k) e *= r;"),
+    # the third RK stage's weights exchanged
+    ("rk_stage3_weights", "solver.c",
+     "U[k] = (1.0 / 3.0) * U[k] + (2.0 / 3.0) * (U2[k] + dt * Lk[k]);",
+     "U[k] = (2.0 / 3.0) * U[k] + (1.0 / 3.0) * (U2[k] + dt * Lk[k]);"),
+    # E_0 = E_1 of Eq.(27) with 1/36 instead of 1/45
+    ("E01_constant", "weno_scalar.c",
+     "E[0] = t1 * t1 / 45.0;", "E[0] = t1 * t1 / 36.0;"),
     # Roe splitting speeds taken in the reverse field order
     ("roe_speed_field_order", "face.c",
      "alpha[s] = fabs(lam[s]);", "alpha[s] = fabs(lam[nvar - 1 - s]);"),

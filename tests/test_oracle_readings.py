@@ -261,6 +261,70 @@ def test_z6_llf_speed_is_the_six_cell_maximum(orc, nvar, d, hybrid):
                 assert np.abs(ref2 - ref6).max() > 1e3 * tol
 
 
+@pytest.mark.parametrize("thr", [{}, {"thr_C": 0.3, "thr_alpha": 2, "thr_L": [2.0, 0.7, 1.0]}])
+def test_z4_switch_threshold_of_the_grid(orc, thr):
+    """The switch of Eq.(33) on a grid uses eps_d = C (dx / L_d)^alpha of
+    Eq.(35) with L_d the domain length along d by default (reading Z4;
+    C = 1, alpha = 3), or the constants given: every face field is linear
+    exactly where its sigma^s lies below eps_d.  The field spans sigma over
+    many decades, so thresholds a factor dx/L apart flag different faces."""
+    nx, ny = 37, 23
+    rng = np.random.default_rng(44)
+    U, dx, _ = w.four_quadrant_2d(nx, ny, 5)
+    U = np.ascontiguousarray(U * (1.0 + 0.01 * rng.standard_normal(U.shape)))
+    p = orc.params(nx, ny, 1, dx, **thr)
+    C0 = thr.get("thr_C", 1.0)
+    al = thr.get("thr_alpha", 3)
+    Ls = thr.get("thr_L", [nx * dx, ny * dx, 1.0])
+    n_between = 0
+    for d in range(2):
+        eps = C0 * (dx / Ls[d]) ** al
+        fl, sg = orc.face_debug(U, dx, G, p, d)
+        np.testing.assert_array_equal(fl, (sg < eps).astype(np.uint8))
+        n_between += int(((sg >= eps) & (sg < eps * Ls[d] / dx)).sum())
+    assert n_between > 10
+
+
+@pytest.mark.parametrize("nvar,d", CASES)
+@pytest.mark.parametrize("c_reg", [1.0, 40.0])
+def test_weno_face_takes_lambda_c_sigma(orc, nvar, d, c_reg):
+    """The WENO branch of a face with the regularization of Eq.(32):
+    lambda^s = c sigma^s, with sigma^s = (dv^s / rho~)^2 (Eq.(30)), dv^s =
+    L^s dU5 / 60 (Eq.(31)), dU5 the fifth difference of the six states and
+    rho~ = sqrt(rho_j rho_{j+1}).  The flux equals the back-projection of the
+    scalar reconstructions (pinned separately) of the split characteristic
+    fluxes with those lambda, and differs from the one with lambda =
+    c sqrt(sigma^s)."""
+    rng = np.random.default_rng(800 + 7 * nvar + d + int(c_reg))
+    p = orc.params(8, 1, 1, 0.1, hybrid=2, c_reg=c_reg)
+    taps = np.array([1.0, -5.0, 10.0, -10.0, 5.0, -1.0])
+    n_apart = 0
+    for _ in range(10):
+        U6 = np.array([rand_state(rng, nvar, 0.8) for _ in range(6)])
+        L, R, _, _ = orc.roe_eigen(nvar, d, G, U6[2], U6[3])
+        F6 = np.array([orc.phys_flux(nvar, d, G, u)[0] for u in U6])
+        a6 = np.array([cell_speeds(u, nvar, d) for u in U6]).max(axis=0)
+        sigma = (L @ (taps @ U6) / 60.0 / np.sqrt(U6[2, 0] * U6[3, 0])) ** 2
+        v, g = U6 @ L.T, F6 @ L.T
+
+        def flux(lam):
+            fs = np.zeros(nvar)
+            for k in range(nvar):
+                fp = 0.5 * (g[:, k] + a6[k] * v[:, k])
+                fm = 0.5 * (g[:, k] - a6[k] * v[:, k])
+                fs[k] = (orc.weno_l2is(fp[0:5], lam[k], p.eps_w)[0] +
+                         orc.weno_l2is(fm[::-1][0:5], lam[k], p.eps_w)[0])
+            return R @ fs
+
+        ref = flux(c_reg * sigma)
+        F, fl, sg = orc.face_flux(nvar, d, G, p, 1e-7, U6)
+        tol = 1e-12 * (1 + np.abs(ref).max())
+        np.testing.assert_allclose(F, ref, rtol=0, atol=tol)
+        np.testing.assert_allclose(sg, sigma, rtol=1e-12, atol=1e-300)
+        n_apart += int(np.abs(flux(c_reg * np.sqrt(sigma)) - ref).max() > 1e3 * tol)
+    assert n_apart >= 5
+
+
 def roe_eigenvalues(UL, UR, nvar, d):
     """u_n - c~, u_n (nvar - 2 times), u_n + c~ at the Roe state of two
     cells: velocity and total enthalpy averaged with sqrt(rho) weights,
