@@ -26,7 +26,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 PINS = ["tests/test_oracle_scalar.py", "tests/test_oracle_face.py", "tests/test_oracle_readings.py",
-        "tests/test_oracle_solutions.py", "tests/test_oracle_dmr.py"]
+        "tests/test_oracle_solutions.py", "tests/test_oracle_dmr.py", "tests/test_oracle_inflow.py"]
+# the jet's 1000-step robustness record is left out of the children (it pins
+# no quantity of the definitions, and alone would take minutes on one thread)
+PIN_FILTER = "not robustness"
 
 # (name, file, text as written, planted mistake)
 MUTANTS = [
@@ -90,6 +93,16 @@ MUTANTS = [
     # E_0 = E_1 of Eq.(27) with 1/36 instead of 1/45
     ("E01_constant", "weno_scalar.c",
      "E[0] = t1 * t1 / 45.0;", "E[0] = t1 * t1 / 36.0;"),
+    # transmissive ghosts copying the second cell of the upper side
+    ("transmissive_hi_index", "solver.c",
+     "if (bchi == ORC_BC_TRANSMISSIVE) return n - 1;", "if (bchi == ORC_BC_TRANSMISSIVE) return n - 2;"),
+    # periodic ghosts of the upper side shifted by one cell
+    ("periodic_hi_index", "solver.c",
+     "if (bchi == ORC_BC_PERIODIC) return k % n;", "if (bchi == ORC_BC_PERIODIC) return (k + 1) % n;"),
+    # the time step blind to the speed of the inflow ghost states (Z24)
+    ("cfl_without_inflow_speed", "solver.c",
+     "      if (s > smax) smax = s;\n    }\n  }\n  *dt = p->cfl * dx / smax;",
+     "      if (s > smax && 0) smax = s;\n    }\n  }\n  *dt = p->cfl * dx / smax;"),
     # Roe splitting speeds taken in the reverse field order
     ("roe_speed_field_order", "face.c",
      "alpha[s] = fabs(lam[s]);", "alpha[s] = fabs(lam[nvar - 1 - s]);"),
@@ -125,7 +138,7 @@ def test_planted_mistakes_fail_a_pin(tmp_path):
         pyoracle.build(src_dir=str(d), out=lib)
         env = dict(os.environ, ORACLE_L2IS_LIB=lib, OMP_NUM_THREADS="1")
         cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-               "-m", "not gpu", *PINS]
+               "-m", "not gpu", "-k", PIN_FILTER, *PINS]
         procs.append((name, subprocess.Popen(cmd, cwd=ROOT, env=env, stdout=subprocess.PIPE,
                                              stderr=subprocess.STDOUT, text=True)))
     survived = []

@@ -261,6 +261,43 @@ def test_z6_llf_speed_is_the_six_cell_maximum(orc, nvar, d, hybrid):
                 assert np.abs(ref2 - ref6).max() > 1e3 * tol
 
 
+@pytest.mark.parametrize("shape", [(31, 1, 1), (17, 13, 1), (9, 8, 7)])
+@pytest.mark.parametrize("split,hybrid", [(0, 0), (1, 0), (2, 2)])
+def test_z16_transmissive_sides_equal_a_grid_padded_by_copies(orc, shape, split, hybrid):
+    """Transmissive sides (reading Z16): the three ghost cells beyond a side
+    hold copies of the boundary cell, so the right-hand side equals the
+    interior of the grid padded by three copies of each boundary cell (with
+    the grid's own threshold lengths), bit for bit; the face fields of the
+    sides are flagged alike."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(1600 + nx + split)
+    nvar = 2 + (1 + (ny > 1) + (nz > 1))
+    dim = nvar - 2
+    U = np.zeros((nvar, nz, ny, nx))
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                U[:, iz, iy, ix] = rand_state(rng, nvar, 0.6)
+    dx = 0.07
+    L = [nx * dx, ny * dx, nz * dx]
+    p = orc.params(nx, ny, nz, dx, bc=[1] * 6, split=split, hybrid=hybrid, thr_L=L)
+    got = orc.rhs(U, dx, G, p)
+    pad = [(0, 0)] + [(3, 3) if n > 1 else (0, 0) for n in (nz, ny, nx)]
+    E = np.ascontiguousarray(np.pad(U, pad, mode="edge"))
+    ez, ey, ex = E.shape[1:]
+    pe = orc.params(ex, ey, ez, dx, bc=[0] * 6, split=split, hybrid=hybrid, thr_L=L)
+    ref = orc.rhs(E, dx, G, pe)
+    sl = tuple(slice(3, -3) if n > 1 else slice(None) for n in (nz, ny, nx))
+    # (global LF over the padded grid: the copies add no new speed; the
+    # periodic wrap of the padded grid reaches no face of the interior)
+    assert np.array_equal(got, ref[(slice(None),) + sl])
+    for d in range(dim):
+        # faces along d: the padded grid's faces 3 .. n_d + 3
+        fl, sg = orc.face_debug(U, dx, G, p, d)
+        fe, se = orc.face_debug(E, dx, G, pe, d)
+        assert np.array_equal(fl, fe[(slice(None),) + sl]) and np.array_equal(sg, se[(slice(None),) + sl])
+
+
 @pytest.mark.parametrize("thr", [{}, {"thr_C": 0.3, "thr_alpha": 2, "thr_L": [2.0, 0.7, 1.0]}])
 def test_z4_switch_threshold_of_the_grid(orc, thr):
     """The switch of Eq.(33) on a grid uses eps_d = C (dx / L_d)^alpha of
