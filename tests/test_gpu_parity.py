@@ -1235,15 +1235,17 @@ def _dmr_case(orc, capi, nx, ny, **kw):
 
 @pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("t", [0.0, 0.031])
-def test_dmr_rhs_parity(orc, capi, path, t):
+@pytest.mark.parametrize("split", [1, 0, 2])
+def test_dmr_rhs_parity(orc, capi, path, t, split):
     """Right-hand side with the state sides of the double Mach reflection
     (a wall from x = 0.1667 on, post-shock ghosts left of it; the exact
     moving shock on the top at the clock's time), through the row kernel
     and the sweeps, on the initial state and on a state the oracle has
-    advanced."""
+    advanced; global LF (the workload's splitting), LLF and Roe splitting
+    (each its own row-kernel build)."""
     import torch
-    say(f"[dmr rhs] path={path} t={t}")
-    U, dx, po, pg, inf = _dmr_case(orc, capi, 128, 32)
+    say(f"[dmr rhs] path={path} t={t} split={split}")
+    U, dx, po, pg, inf = _dmr_case(orc, capi, 128, 32, split=split)
     if t > 0:
         tt, n, st = orc.run(U, dx, G, po, t)
         assert st == 0 and tt == t
