@@ -345,11 +345,12 @@ int fused_zchunk(const weno_l2is_ctx* c) {
   if (c->zchunk > 0) return c->zchunk < nz ? c->zchunk : nz;
   const long long tiles = (long long)((c->n[0] + FT_X - 1) / FT_X) * ((c->n[1] + FT_Y - 1) / FT_Y);
   const long long cap = (long long)(c->n_cu > 0 ? c->n_cu : 256) * (c->wpe == 1 ? 1 : 2);
-  if (tiles * ((nz + 15) / 16) < 3 * cap) {
+  const auto halving = [&]() {
     int zc = nz;
     while (zc > 16 && tiles * ((nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
     return zc;
-  }
+  };
+  if (tiles * ((nz + 15) / 16) < 3 * cap) return halving();
   int best = 0;
   double best_score = -1.0;
   for (int k = (nz + 127) / 128; k <= nz / 16; ++k) {
@@ -363,7 +364,7 @@ int fused_zchunk(const weno_l2is_ctx* c) {
       best = zc;
     }
   }
-  return best > 0 ? best : 32;
+  return best > 0 ? best : halving();  // (no balanced chunk of 16..128 planes)
 }
 
 hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
