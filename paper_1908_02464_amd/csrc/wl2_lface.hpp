@@ -294,11 +294,9 @@ __device__ __forceinline__ double weno_l2is_lr(double fm2, double fm1, double f0
 // (Eq.(22)-(23)); the change with respect to the linear flux of that field is
 // back-projected (Eq.(24)).  Only one row and twelve split values are live.
 // W: the weighting (W_*) fixed at compile time, or -1 to read ph.weights.
-template <int NV, int DIR, int K, int W, class Src>
-__device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, double al, double dvk,
-                                             double LFk, const KPhys& ph) {
-  double r[NV];
-  left_row<NV, DIR, K>(s, r);
+template <int NV, int DIR, int W, class Src>
+__device__ __forceinline__ double lean_field_row(const Src& src, const double (&r)[NV], const Roe<NV>& s,
+                                                 double al, double dvk, double LFk, const KPhys& ph) {
   double fp[6], fm[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
@@ -319,6 +317,43 @@ __device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, d
   return fw - (LFk + al * dvk);
 }
 
+template <int NV, int DIR, int K, int W, class Src>
+__device__ __forceinline__ double lean_field(const Src& src, const Roe<NV>& s, double al, double dvk,
+                                             double LFk, const KPhys& ph) {
+  double r[NV];
+  left_row<NV, DIR, K>(s, r);
+  return lean_field_row<NV, DIR, W>(src, r, s, al, dvk, LFk, ph);
+}
+
+// Row k of L for a field k known only at run time: each candidate row with
+// the expressions of left_row<NV, DIR, k>, then selected (the same bits, no
+// branch for lanes that take different fields).
+template <int NV, int DIR>
+__device__ __forceinline__ void left_row_rt(const Roe<NV>& s, int k, double (&r)[NV]) {
+  constexpr int DIM = NV - 2;
+  const double sg = k == 0 ? 1.0 : -1.0;
+  double ac[NV], en[NV], sh[NV];
+  ac[0] = 0.5 * (s.b2 + sg * s.u[DIR] * s.ic);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) ac[1 + j] = 0.5 * (-s.b1 * s.u[j] - (j == DIR ? sg * s.ic : 0.0));
+  ac[NV - 1] = 0.5 * s.b1;
+  en[0] = 1.0 - s.b2;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) en[1 + j] = s.b1 * s.u[j];
+  en[NV - 1] = -s.b1;
+  const int comp = (k - 2 < DIR) ? k - 2 : k - 1;  // shear field k-2: its momentum component
+  double uc = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) uc = j == comp ? s.u[j] : uc;
+  sh[0] = -uc * s.ic;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) sh[1 + j] = (j == comp) ? s.ic : 0.0;
+  sh[NV - 1] = 0.0;
+  const bool acoustic = k == 0 || k == NV - 1;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r[i] = acoustic ? ac[i] : (k == 1 ? en[i] : sh[i]);
+}
+
 template <int NV, int DIR, int W = -1, class Src>
 __device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, const FaceState<NV>& st,
                                                 const KPhys& ph, double (&dF)[NV]) {
@@ -334,16 +369,13 @@ __device__ __forceinline__ void lean_correction(const Src& src, unsigned mask, c
   back_project<NV, DIR>(st.s, del, dF);
 }
 
-// Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
-// the face below the cell, side 1 the face above.  Returns the change of the
-// face flux (WENO minus linear, Eq.(33) per field).
-template <int NV, int DIR, int SPLIT, int HYB, int W = -1>
-__device__ __forceinline__ void face_delta(const double* U, const KGrid& g, const KPhys& ph,
-                                           const unsigned long long* lfb, int x, int y, int z,
-                                           int side, double (&dF)[NV]) {
-  // the six stencil cells, loaded once (all loads issued before any use) and
-  // kept in registers for the linear flux and every field's correction; the
-  // face below the cell starts 3 cells below it, the face above 2 below
+// The six stencil cells of the face of cell (x, y, z) along DIR below it
+// (side 0) or above it (side 1) as light records, with the boundary ghosts
+// (all loads issued before any use).
+template <int NV, int DIR>
+__device__ __forceinline__ void face_stencil(const double* U, const KGrid& g, const KPhys& ph, int x,
+                                             int y, int z, int side, LRec<NV> (&w)[6]) {
+  // the face below the cell starts 3 cells below it, the face above 2 below
   const int c0 = (DIR == 0 ? x : DIR == 1 ? y : z) + (side ? -2 : -3);
   double u[6][NV];
   bool flip[6];
@@ -356,7 +388,6 @@ __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, cons
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[m][v] = U[v * g.ncell + off];
   }
-  LRec<NV> w[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     if (flip[m]) u[m][1 + DIR] = -u[m][1 + DIR];
@@ -366,12 +397,66 @@ __device__ __forceinline__ void face_delta(const double* U, const KGrid& g, cons
       load_yghost<NV>(g, x, c0 + m, u[m]);
     make_lrec<NV>(u[m], ph, w[m]);
   }
+}
+
+// Nonlinear correction of one face of cell (x, y, z) along DIR: side 0 is
+// the face below the cell, side 1 the face above.  Returns the change of the
+// face flux (WENO minus linear, Eq.(33) per field).
+template <int NV, int DIR, int SPLIT, int HYB, int W = -1>
+__device__ __forceinline__ void face_delta(const double* U, const KGrid& g, const KPhys& ph,
+                                           const unsigned long long* lfb, int x, int y, int z,
+                                           int side, double (&dF)[NV]) {
+  // the six stencil cells, kept in registers for the linear flux and every
+  // field's correction
+  LRec<NV> w[6];
+  face_stencil<NV, DIR>(U, g, ph, x, y, z, side, w);
   const WinSrc<NV> src{w[0], w[1], w[2], w[3], w[4], w[5]};
   double Flin[NV];
   FaceState<NV> st;
   const unsigned mask = face_linear_st<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin, st);
   if (mask) {
     lean_correction<NV, DIR, W>(src, mask, st, ph, dF);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+  }
+}
+
+// The same change of flux computed by NV lanes of one wavefront, lane k of
+// them (the lanes lane0 .. lane0 + NV - 1, all active here) taking field k:
+// each forms the linear face and the correction of its own field, and the
+// lanes exchange those to back-project them.  Every lane ends with the bits
+// face_delta gives (the same operations per field, summed alike).
+template <int NV, int DIR, int SPLIT, int HYB, int W = -1>
+__device__ __forceinline__ void face_delta_field(const double* U, const KGrid& g, const KPhys& ph,
+                                                 const unsigned long long* lfb, int x, int y, int z,
+                                                 int side, int k, int lane0, double (&dF)[NV]) {
+  LRec<NV> w[6];
+  face_stencil<NV, DIR>(U, g, ph, x, y, z, side, w);
+  const WinSrc<NV> src{w[0], w[1], w[2], w[3], w[4], w[5]};
+  double Flin[NV];
+  FaceState<NV> st;
+  const unsigned mask = face_linear_st<NV, DIR, SPLIT, HYB>(src, ph, ph.eps_thr[DIR], lfb, Flin, st);
+  double LF[NV];
+  project<NV, DIR>(st.s, st.Fc6, LF);
+  double al = st.a[0], dvk = st.dv[0], LFk = LF[0];
+#pragma unroll
+  for (int j = 1; j < NV; ++j) {
+    al = j == k ? st.a[j] : al;
+    dvk = j == k ? st.dv[j] : dvk;
+    LFk = j == k ? LF[j] : LFk;
+  }
+  double mine = 0.0;
+  if ((mask >> k) & 1u) {
+    double r[NV];
+    left_row_rt<NV, DIR>(st.s, k, r);
+    mine = lean_field_row<NV, DIR, W>(src, r, st.s, al, dvk, LFk, ph);
+  }
+  double del[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) del[j] = __shfl(mine, lane0 + j, 64);
+  if (mask) {
+    back_project<NV, DIR>(st.s, del, dF);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) dF[v] = 0.0;

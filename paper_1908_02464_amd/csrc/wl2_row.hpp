@@ -367,8 +367,90 @@ __device__ __forceinline__ bool row_fix_cell(const double* Uk, double* out, cons
   return true;
 }
 
-// Single grid.  A list that gives every group at most one cell is taken
-// FIX_GRP lanes per cell (latency), a longer one a lane per cell (throughput).
+// Listed cells per workgroup round of the field-parallel mode: the two
+// wavefronts of a 2D workgroup take the x and the y faces of 8 cells, one
+// lane per (side, field) pair (8 of them); in 1D each takes 8 cells' x faces
+// (6 lanes each).
+template <int NV>
+constexpr int fix_fields_cells() { return NV == 4 ? 8 : 16; }
+
+// Field-parallel corrections of a short list (every cell in flight at once):
+// each flagged face's change is formed by NV lanes, one per field
+// (face_delta_field), a wavefront running one direction only, so a lane's
+// work is the linear face and one field's WENO flux where one lane per face
+// runs every flagged field and both directions one after the other.  The
+// changes meet in LDS and are summed per cell in the fixed order x-, x+, y-,
+// y+ as serial_correction sums them: the same bits.
+template <int NV, int OUT, int SPLIT, int HYB>
+__device__ __forceinline__ void row_fix_fields(const RowArgs& a, const KGrid& g, const KPhys& ph,
+                                               unsigned int n, double scale, double& cfl_max,
+                                               bool& cfl_bad) {
+  constexpr int NF = 2 * (NV - 2);
+  constexpr int CPB = fix_fields_cells<NV>();
+  __shared__ double sdf[CPB][NF][NV];
+  const int lane = threadIdx.x & 63;
+  const int dir = NV == 4 ? (int)(threadIdx.x >> 6) : 0;
+  const int cslot = NV == 4 ? (lane >> 3) : (int)(threadIdx.x >> 3);
+  const int j = lane & 7, side = j / NV, k = j % NV;
+  const int f = 2 * dir + side;
+  const bool worker = j < 2 * NV;
+  for (unsigned int base = blockIdx.x * CPB; base < n; base += gridDim.x * CPB) {
+    const unsigned int i = base + cslot;
+    unsigned cm = 0;
+    long long off = 0;
+    if (i < n) {
+      const unsigned long long e = a.list[i];
+      off = (long long)((e >> 8) & 0xffffffffull);
+      cm = (unsigned)(e & 0xffu);
+    }
+    double dF[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+    if (worker && ((cm >> f) & 1u)) {
+      const int x = (int)(off % g.n[0]), y = (int)(off / g.n[0]);
+      const int lane0 = (lane & ~7) + side * NV;
+      if (dir == 0) {
+        face_delta_field<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, 0, side, k, lane0, dF);
+      } else {
+        if constexpr (NV >= 4)
+          face_delta_field<NV, 1, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, 0, side, k, lane0, dF);
+      }
+    }
+    if (worker && k == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sdf[cslot][f][v] = dF[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < CPB && base + threadIdx.x < n) {
+      const unsigned long long e = a.list[base + threadIdx.x];
+      const long long c = (long long)((e >> 8) & 0xffffffffull);
+      const unsigned m = (unsigned)(e & 0xffu);
+      double acc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+      for (int ff = 0; ff < NF; ++ff) {
+        if (!((m >> ff) & 1u)) continue;
+        const double sg = (ff & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += sg * sdf[threadIdx.x][ff][v];
+      }
+      double un[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        un[v] = a.out[v * g.ncell + c] + scale * (acc[v] * ph.inv_dx);
+        a.out[v * g.ncell + c] = un[v];
+      }
+      if (OUT == OUT_RK && a.cfl != nullptr) cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
+    }
+    __syncthreads();  // sdf is free for the next round
+  }
+}
+
+// Single grid.  A list short enough for every cell to be in flight at once
+// takes the field-parallel mode; a list that gives every group at most one
+// cell is taken FIX_GRP lanes per cell (latency), a longer one a lane per
+// cell (throughput).  128 threads per workgroup.
 template <int NV, int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys ph) {
   // the next stage's list starts empty (no kernel of this stage uses it)
@@ -382,18 +464,22 @@ __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys 
   const unsigned int n = *a.list_n;
   const unsigned int threads = gridDim.x * blockDim.x;
   const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool grouped = (unsigned long long)n * FIX_GRP <= FIX_GROUPED_LANES && n <= threads / FIX_GRP;
-  const unsigned int step = grouped ? threads / FIX_GRP : threads;
   double cfl_max = 0.0;
   bool cfl_bad = false;
-  for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
-    const unsigned long long e = a.list[i];
-    double un[NV];
-    const bool wrote = row_fix_cell<NV, SPLIT, HYB>(a.Uk, a.out, a.ctl, g, ph,
-                                                    (long long)((e >> 8) & 0xffffffffull),
-                                                    (unsigned)(e & 0xffu), scale, grouped, un);
-    if (OUT == OUT_RK && a.cfl != nullptr && wrote)
-      cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
+  if ((unsigned long long)n <= (unsigned long long)gridDim.x * fix_fields_cells<NV>()) {
+    row_fix_fields<NV, OUT, SPLIT, HYB>(a, g, ph, n, scale, cfl_max, cfl_bad);
+  } else {
+    const bool grouped = (unsigned long long)n * FIX_GRP <= FIX_GROUPED_LANES && n <= threads / FIX_GRP;
+    const unsigned int step = grouped ? threads / FIX_GRP : threads;
+    for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
+      const unsigned long long e = a.list[i];
+      double un[NV];
+      const bool wrote = row_fix_cell<NV, SPLIT, HYB>(a.Uk, a.out, a.ctl, g, ph,
+                                                      (long long)((e >> 8) & 0xffffffffull),
+                                                      (unsigned)(e & 0xffu), scale, grouped, un);
+      if (OUT == OUT_RK && a.cfl != nullptr && wrote)
+        cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
+    }
   }
   if (OUT == OUT_RK && a.cfl != nullptr) cfl_commit_wave(a.cfl, cfl_max, cfl_bad);
 }

@@ -1370,3 +1370,98 @@ def test_dmr_paper_grid_run(capi):
     assert abs(xs - exact) < 1.5 * dx
     assert 15.0 < rho.max() < 25.0 and rho.min() > 1.39
     assert np.all(np.abs(rho[:, -16:] - 1.4) < 1e-6)
+
+
+def _block_pattern(rng, shape, block):
+    """Piecewise-constant random states on blocks of `block` cells per
+    direction: strong jumps a few cells apart, so that most cells are listed
+    for the nonlinear correction."""
+    nx, ny = shape
+    dim = 2 if ny > 1 else 1
+    bx, by = nx // block, max(ny // block, 1)
+    rho = rng.uniform(0.5, 2.0, (by, bx))
+    p = rng.uniform(0.5, 2.0, (by, bx))
+    vel = [rng.uniform(-0.5, 0.5, (by, bx)) for _ in range(dim)]
+    up = lambda a: np.repeat(np.repeat(a, block if ny > 1 else 1, 0), block, 1)[:ny, :nx]
+    U = w.conserved(up(rho), [up(v) for v in vel], up(p), G)
+    return np.ascontiguousarray(U.reshape(dim + 2, 1, ny, nx))
+
+
+def _listed_cells(capi, ctx, Ud, shape):
+    """Cells with at least one face whose detector asks for the WENO flux."""
+    import torch
+    nx, ny = shape
+    nv = Ud.shape[0]
+    listed = np.zeros((ny, nx), bool)
+    for d in range(2 if ny > 1 else 1):
+        nf = nx * ny // shape[d] * (shape[d] + 1)
+        fl = torch.zeros(nv * nf, dtype=torch.uint8, device="cuda")
+        sg = torch.zeros(nv * nf, dtype=torch.float64, device="cuda")
+        ctx.face_debug(Ud, d, fl, sg)
+        torch.cuda.synchronize()
+        nonlin = (fl.cpu().numpy().reshape(nv, -1) == 0).any(0)  # flag 1: linear flux
+        if d == 0:
+            a = nonlin.reshape(ny, nx + 1)
+            listed |= a[:, :-1] | a[:, 1:]
+        else:
+            a = nonlin.reshape(ny + 1, nx)
+            listed |= a[:-1] | a[1:]
+    return int(listed.sum())
+
+
+@pytest.mark.parametrize("dim,variant", [(2, "default"), (2, "lf"), (2, "roe"), (2, "hybrid_b01"),
+                                         (2, "per_face"), (1, "default"), (1, "lf")])
+def test_row_correction_modes_bitwise(capi, dim, variant):
+    """The 1D/2D correction kernel takes a list of at most 8192 cells (2D;
+    16384 in 1D) with NV lanes per flagged face, one per field, a list of at
+    most 16384 cells (2D) with one lane per face, and a longer one with one
+    lane per cell; the three must give the same bits.  A periodic pattern
+    and the pattern tiled into a grid of several copies (every copy sees the
+    same stencils, so the same fluxes, global speeds and CFL dt; the length
+    L of the switch threshold, Eq.(35), is the pattern's in every run) put
+    one set of faces into lists of these lengths: dU/dt and one RK3 step of
+    every copy equal the pattern's bit for bit."""
+    import torch
+    rng = np.random.default_rng(4242 + dim)
+    if dim == 2:
+        shape, tiles = (88, 80), [(2, 1), (3, 2)]
+    else:
+        shape, tiles = (800, 1), [(40, 1)]
+    U = _block_pattern(rng, shape, 8)
+    dx = 1.0 / shape[0]
+    say(f"[correction modes] dim={dim} variant={variant} tiles={tiles}")
+
+    thr_L = [shape[0] * dx, shape[1] * dx, dx]
+
+    def run(Uh, shp):
+        p = capi.params_default(shp[0], shp[1], 1, dx, bc=[0] * 6, thr_L=thr_L, **VARIANTS[variant])
+        ctx = capi.Context(shp[0], shp[1], 1, dx, G, p)
+        Ud = to_dev(Uh)
+        n = _listed_cells(capi, ctx, Ud, shp)
+        r = torch.full_like(Ud, float("nan"))
+        ctx.rhs(Ud, r)
+        ctx.step(Ud)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        out = (n, to_host(r), to_host(Ud), ctx.clock())
+        ctx.close()
+        return out
+
+    n0, r0, u0, c0 = run(U, shape)
+    say(f"    pattern {shape}: {n0} listed cells")
+    if dim == 2:
+        assert 4096 < n0 <= 8192  # field-parallel; x2: one lane per face; x6: one lane per cell
+    else:
+        assert n0 * tiles[0][0] > 16384 >= n0
+    for tx, ty in tiles:
+        Ut = np.ascontiguousarray(np.tile(U, (1, 1, ty, tx)))
+        n, r, u, c = run(Ut, (shape[0] * tx, shape[1] * ty))
+        assert n == n0 * tx * ty
+        say(f"    tiled {tx}x{ty}: {n} listed cells")
+        assert c == c0
+        for j in range(ty):
+            for i in range(tx):
+                sl = (slice(None), slice(None), slice(j * shape[1], (j + 1) * shape[1]),
+                      slice(i * shape[0], (i + 1) * shape[0]))
+                assert np.array_equal(r[sl], r0), (i, j)
+                assert np.array_equal(u[sl], u0), (i, j)
