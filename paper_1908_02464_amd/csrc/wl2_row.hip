@@ -51,6 +51,10 @@ hipError_t row_fix(const RowLaunch& L) {
                   L.rk_b, L.list,   L.list_n, 0ull, L.list_clear,
                   L.out_kind == OUT_RK ? L.cfl : nullptr};
   const dim3 fg(1024), fb(128);
+  // the per-cell kernel: 2048 workgroups, so that lists of up to 16384
+  // cells take its field-parallel mode (workgroups past the list's end
+  // return at once)
+  const dim3 fgc(2048);
   if (L.fo_D != nullptr) {
     if (L.nvar != 4) return hipErrorInvalidValue;
 #define WL2_FO(O, S, H)                                                                          \
@@ -75,11 +79,11 @@ hipError_t row_fix(const RowLaunch& L) {
 #define WL2_FIX(NV, O)                                                                     \
   do {                                                                                     \
     if (L.fast == 1)                                                                       \
-      hipLaunchKernelGGL((row_fix_kernel<NV, O, SPLIT_LLF, HYB_PER_FIELD>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, SPLIT_LLF, HYB_PER_FIELD>), fgc, fb, 0, L.stream, a, L.g, L.ph); \
     else if (L.fast == 2)                                                                  \
-      hipLaunchKernelGGL((row_fix_kernel<NV, O, SPLIT_LF, HYB_PER_FIELD>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, SPLIT_LF, HYB_PER_FIELD>), fgc, fb, 0, L.stream, a, L.g, L.ph); \
     else                                                                                   \
-      hipLaunchKernelGGL((row_fix_kernel<NV, O, -1, -1>), fg, fb, 0, L.stream, a, L.g, L.ph); \
+      hipLaunchKernelGGL((row_fix_kernel<NV, O, -1, -1>), fgc, fb, 0, L.stream, a, L.g, L.ph); \
   } while (0)
   if (L.nvar == 3) {
     if (L.out_kind == OUT_RK) WL2_FIX(3, OUT_RK); else WL2_FIX(3, OUT_WRITE);

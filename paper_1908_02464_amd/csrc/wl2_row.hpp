@@ -448,9 +448,9 @@ __device__ __forceinline__ void row_fix_fields(const RowArgs& a, const KGrid& g,
 }
 
 // Single grid.  A list short enough for every cell to be in flight at once
-// takes the field-parallel mode; a list that gives every group at most one
-// cell is taken FIX_GRP lanes per cell (latency), a longer one a lane per
-// cell (throughput).  128 threads per workgroup.
+// (launched with 2048 workgroups: 16384 cells in 2D, 32768 in 1D) takes the
+// field-parallel mode (latency), a longer one a lane per cell (throughput).
+// 128 threads per workgroup.
 template <int NV, int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys ph) {
   // the next stage's list starts empty (no kernel of this stage uses it)
@@ -469,14 +469,12 @@ __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys 
   if ((unsigned long long)n <= (unsigned long long)gridDim.x * fix_fields_cells<NV>()) {
     row_fix_fields<NV, OUT, SPLIT, HYB>(a, g, ph, n, scale, cfl_max, cfl_bad);
   } else {
-    const bool grouped = (unsigned long long)n * FIX_GRP <= FIX_GROUPED_LANES && n <= threads / FIX_GRP;
-    const unsigned int step = grouped ? threads / FIX_GRP : threads;
-    for (unsigned int i = grouped ? tid / FIX_GRP : tid; i < n; i += step) {
+    for (unsigned int i = tid; i < n; i += threads) {
       const unsigned long long e = a.list[i];
       double un[NV];
       const bool wrote = row_fix_cell<NV, SPLIT, HYB>(a.Uk, a.out, a.ctl, g, ph,
                                                       (long long)((e >> 8) & 0xffffffffull),
-                                                      (unsigned)(e & 0xffu), scale, grouped, un);
+                                                      (unsigned)(e & 0xffu), scale, false, un);
       if (OUT == OUT_RK && a.cfl != nullptr && wrote)
         cfl_max = nan_max(cfl_max, cfl_speed_u<NV>(un, ph.gamma, cfl_bad));
     }
@@ -493,7 +491,8 @@ __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys 
 // from the entry of the cell above it (listed, since the face is flagged)
 // or, where that cell is a ghost, computing it.  A face's change of flux has
 // the same bits whichever cell computes it, and the sum is the per-cell
-// kernel's, so the result is bit-identical.
+// kernel's, so the result is bit-identical.  A list short enough for all of
+// its faces' fields to be in flight at once takes phase A field-parallel.
 template <int NV, int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void row_face_kernel(RowArgs a, KGrid g, KPhys ph, double* D,
                                                        unsigned int* map, unsigned int cap) {
@@ -503,6 +502,36 @@ __global__ __launch_bounds__(128) void row_face_kernel(RowArgs a, KGrid g, KPhys
   constexpr int ND = NV - 2;
   const unsigned int n = *a.list_n;
   const unsigned int threads = gridDim.x * blockDim.x;
+  if ((unsigned long long)ND * n * NV <= threads) {
+    // a short list: NV lanes per face, one per field (face_delta_field),
+    // every face in flight at once; groups of NV consecutive lanes
+    // (direction-major, then entry), so a group never straddles wavefronts
+    const unsigned int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ND * n * NV) return;
+    const unsigned int q = i / NV, kf = i - q * NV;
+    const unsigned int dir = q / n, k = q - dir * n;
+    const unsigned long long e = a.list[k];
+    const long long off = (long long)((e >> 8) & 0xffffffffull);
+    const unsigned cm = (unsigned)(e & 0xffu);
+    if (dir == 0 && kf == 0) map[off] = k;
+    if (!((cm >> (2 * dir)) & 1u)) return;
+    const int x = (int)(off % g.n[0]);
+    const int y = (int)(off / g.n[0]);
+    const int lane0 = (int)(threadIdx.x & 63) - (int)kf;
+    double dF[NV];
+    if (dir == 0) {
+      face_delta_field<NV, 0, SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[0], x, y, 0, 0, (int)kf, lane0, dF);
+    } else {
+      if constexpr (NV >= 4)
+        face_delta_field<NV, (NV >= 4 ? 1 : 0), SPLIT, HYB>(a.Uk, g, ph, a.ctl->lf_bits[1], x, y, 0, 0,
+                                                            (int)kf, lane0, dF);
+    }
+    double val = dF[0];
+#pragma unroll
+    for (int v = 1; v < NV; ++v) val = v == (int)kf ? dF[v] : val;
+    D[((size_t)dir * NV + kf) * cap + k] = val;  // lane kf writes value kf
+    return;
+  }
   // lanes ordered direction-major, so a wavefront takes faces of one direction
   for (unsigned int i = blockIdx.x * blockDim.x + threadIdx.x; i < ND * n; i += threads) {
     const unsigned int dir = i / n, k = i - dir * n;
