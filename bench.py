@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -228,10 +229,18 @@ def other_configs(torch, capi, workloads):
             if nsteps:
                 ctx.advance(Ud, nsteps, t_end)
             else:
+                # calls of up to 256 steps; once the clock is near t_end the
+                # next call asks for about the steps left at the latest dt
+                # (a step past t_end still launches its kernels, which return
+                # at once)
+                chunk = 256
                 while True:
-                    ctx.advance(Ud, 256, t_end)
-                    if not ctx.time()[0] < t_end or ctx.status() != 0:
+                    ctx.advance(Ud, chunk, t_end)
+                    t_now, dt_now = ctx.time()
+                    if not t_now < t_end or ctx.status() != 0:
                         break
+                    if dt_now > 0.0:
+                        chunk = max(1, min(256, int(math.ceil((t_end - t_now) / dt_now * 1.05)) + 1))
             e1.record(ctx.stream)
             e1.synchronize()
             t, _, steps = ctx.clock()
