@@ -88,12 +88,12 @@ struct YGhostRule {
   double geom[4];
 };
 
-[[maybe_unused]] static __global__ void ghost_fill_kernel(const double* __restrict__ U, KGrid g,
-                                                          const StepCtl* ctl, double tc, double dx,
-                                                          YGhostRule rule, double* lo, double* hi) {
+// Ghost value i of the 2 x 3 x nx (side, layer, column) of the y sides.
+__device__ __forceinline__ void ghost_fill_item(const double* __restrict__ U, const KGrid& g,
+                                                const StepCtl* ctl, double tc, double dx,
+                                                const YGhostRule& rule, double* lo, double* hi,
+                                                long long i) {
   const long long nx = g.n[0], ny = g.n[1];
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= 2 * 3 * nx) return;
   const int side = (int)(i / (3 * nx));
   const int layer = (int)((i / nx) % 3);
   const long long x = i % nx;
@@ -121,6 +121,14 @@ struct YGhostRule {
   for (int v = 0; v < 4; ++v) b[((long long)layer * 4 + v) * nx + x] = u[v];
 }
 
+[[maybe_unused]] static __global__ void ghost_fill_kernel(const double* __restrict__ U, KGrid g,
+                                                          const StepCtl* ctl, double tc, double dx,
+                                                          YGhostRule rule, double* lo, double* hi) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= 2 * 3 * (long long)g.n[0]) return;
+  ghost_fill_item(U, g, ctl, tc, dx, rule, lo, hi, i);
+}
+
 // Program the device clock target (enqueued, no host synchronisation) and
 // clear the running CFL maximum.
 [[maybe_unused]] static __global__ void set_t_end_kernel(StepCtl* ctl, double t_end) {
@@ -134,13 +142,23 @@ struct YGhostRule {
 // |u_d - c|, |u_d|, |u_d + c| (fields u-c, entropy/shear, u+c), folded into
 // the block's slot of ctl->lf_slots.  fmax passes over a NaN speed, as the
 // oracle's comparison does (a non-physical cell stops the run through the
-// CFL status instead).
-template <int NV>
+// CFL status instead).  GHOST: the same launch also fills the ghost rows of
+// the y state sides of this stage (ghost_fill_item), which the speeds do
+// not read.
+template <int NV, bool GHOST>
 __global__ __launch_bounds__(RED_BLOCK) void lf_reduce_kernel(const double* __restrict__ U,
                                                               long long ncell, double gamma,
-                                                              StepCtl* ctl) {
+                                                              StepCtl* ctl, KGrid g, double tc,
+                                                              double dx, YGhostRule rule,
+                                                              double* lo, double* hi) {
   constexpr int DIM = NV - 2;
   __shared__ double sh[RED_BLOCK / 64][3 * DIM];
+  if (GHOST) {
+    const long long ng = 2 * 3 * (long long)g.n[0];
+    for (long long i = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; i < ng;
+         i += (long long)gridDim.x * RED_BLOCK)
+      ghost_fill_item(U, g, ctl, tc, dx, rule, lo, hi, i);
+  }
   double mx[DIM][3];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) mx[d][0] = mx[d][1] = mx[d][2] = 0.0;

@@ -131,15 +131,19 @@ bool has_state_sides(const weno_l2is_params* p, int dim) {
 
 // Ghost rows of the y state sides for the state Uk, at the stage time
 // t0 + tc dt (tc < 0: the clock's t).
-hipError_t fill_yghosts(const weno_l2is_ctx* c, const double* Uk, double tc) {
-  if (!c->ygh) return hipSuccess;
+YGhostRule ghost_rule(const weno_l2is_ctx* c) {
   YGhostRule r;
   for (int s = 0; s < 2; ++s)
     for (int v = 0; v < 4; ++v) r.state[s][v] = c->p.bstate[s][v];
   for (int i = 0; i < 4; ++i) r.geom[i] = c->p.bgeom[i];
+  return r;
+}
+
+hipError_t fill_yghosts(const weno_l2is_ctx* c, const double* Uk, double tc) {
+  if (!c->ygh) return hipSuccess;
   const long long n = 2ll * 3 * c->n[0];
   hipLaunchKernelGGL(ghost_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, Uk,
-                     c->g, c->ctl, tc, c->dx, r, const_cast<double*>(c->g.ygh[0]),
+                     c->g, c->ctl, tc, c->dx, ghost_rule(c), const_cast<double*>(c->g.ygh[0]),
                      const_cast<double*>(c->g.ygh[1]));
   return hipGetLastError();
 }
@@ -221,13 +225,27 @@ hipError_t launch_cfl(const weno_l2is_ctx* c, const double* U, double dt_fixed, 
 // Global LF speeds of U: per-block maxima into the slots, then the maximum
 // over the slots into ctl->lf_bits (the slots are zero between reductions:
 // the control block starts zeroed and the finalize kernel clears them).
-hipError_t launch_lf(const weno_l2is_ctx* c, const double* U) {
+// With y state sides the reduction's launch also fills their ghost rows for
+// stage time tc (as fill_yghosts).
+hipError_t launch_lf(const weno_l2is_ctx* c, const double* U, double tc) {
   const unsigned b = red_blocks(c->ncell);
-  switch (c->nvar) {
-    case 3: hipLaunchKernelGGL(lf_reduce_kernel<3>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
-    case 4: hipLaunchKernelGGL(lf_reduce_kernel<4>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
-    default: hipLaunchKernelGGL(lf_reduce_kernel<5>, dim3(b), dim3(RED_BLOCK), 0, c->stream, U, c->ncell, c->gamma, c->ctl); break;
+  double* lo = const_cast<double*>(c->g.ygh[0]);
+  double* hi = const_cast<double*>(c->g.ygh[1]);
+  const YGhostRule r = ghost_rule(c);
+#define WL2_LFR(NV, GH)                                                                      \
+  hipLaunchKernelGGL((lf_reduce_kernel<NV, GH>), dim3(b), dim3(RED_BLOCK), 0, c->stream, U, \
+                     c->ncell, c->gamma, c->ctl, c->g, tc, c->dx, r, lo, hi)
+  if (c->ygh) {
+    if (c->nvar != 4) return hipErrorInvalidValue;
+    WL2_LFR(4, true);
+  } else if (c->nvar == 3) {
+    WL2_LFR(3, false);
+  } else if (c->nvar == 4) {
+    WL2_LFR(4, false);
+  } else {
+    WL2_LFR(5, false);
   }
+#undef WL2_LFR
   hipLaunchKernelGGL(lf_finalize_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, c->nvar);
   return hipGetLastError();
 }
@@ -409,8 +427,8 @@ hipError_t launch_fused(const weno_l2is_ctx* c, int out_kind, const double* Uk, 
 // dU/dt of the state Uk into out (WRITE then ACCUM over directions).
 hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
   hipError_t e;
-  if ((e = fill_yghosts(c, Uk, -1.0)) != hipSuccess) return e;
-  if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
+  e = c->p.split == WL2_SPLIT_LF ? launch_lf(c, Uk, -1.0) : fill_yghosts(c, Uk, -1.0);
+  if (e != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
   if (use_row(c)) return launch_row(c, OUT_WRITE, Uk, out, nullptr, 0.0, 1.0);
   for (int d = 0; d < c->dim; ++d) {
@@ -426,8 +444,8 @@ hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
 hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, double* out,
                  double ra, double rb, double tc, bool fold_cfl = false) {
   hipError_t e;
-  if ((e = fill_yghosts(c, Uk, tc)) != hipSuccess) return e;
-  if (c->p.split == WL2_SPLIT_LF && (e = launch_lf(c, Uk)) != hipSuccess) return e;
+  e = c->p.split == WL2_SPLIT_LF ? launch_lf(c, Uk, tc) : fill_yghosts(c, Uk, tc);
+  if (e != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
   if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
   for (int d = 0; d < c->dim - 1; ++d) {
