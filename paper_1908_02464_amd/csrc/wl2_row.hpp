@@ -624,8 +624,9 @@ __global__ __launch_bounds__(128) void row_sum_kernel(RowArgs a, KGrid g, KPhys 
 // the clock rule of finalize_dt_kernel, then per stage the row items (item
 // k on wavefront k mod W, every wavefront taking the same number of items,
 // past the grid edge owning no cell) and the corrections of the listed
-// cells, with workgroup barriers between.  The same row_item and
-// row_fix_cell code as the multi-launch path: the same bits.
+// cells (field-parallel for up to nthr / 16 cells), with workgroup
+// barriers between.  The same row_item, face_delta_field and row_fix_cell
+// code as the multi-launch path: the same bits.
 struct RowStepsArgs {
   double* U;             // state, advanced in place
   double* U1;            // stage states
@@ -698,13 +699,59 @@ __global__ __launch_bounds__(W * RW) void row1d_steps_kernel(RowStepsArgs s, KGr
         row_item<NV, OUT_RK, SPLIT, HYB>(a, g, ph, buf[wave], nullptr, (wave + k * W) * RT, 0, 1, dt);
       __syncthreads();
       const unsigned int nl = list_n;
-      const bool grouped = (unsigned long long)nl * FIX_GRP <= (unsigned long long)nthr;
-      const unsigned int stride = grouped ? nthr / FIX_GRP : nthr;
-      for (unsigned int i = grouped ? threadIdx.x / FIX_GRP : threadIdx.x; i < nl; i += stride) {
-        const unsigned long long e = s.list[i];
-        double un[NV];
-        row_fix_cell<NV, SPLIT, HYB>(Uk, out, ctl, g, ph, (long long)((e >> 8) & 0xffffffffull),
-                                     (unsigned)(e & 0xffu), rb * dt, grouped, un);
+      if (nl == 0u) {
+        // nothing listed
+      } else if ((unsigned long long)nl * 8u <= (unsigned long long)nthr / 2u) {
+        // a list this short leaves the workgroup's SIMDs mostly idle:
+        // field-parallel, 8 lanes per listed cell (one wavefront holds the
+        // group), lane (side, field) of the first six forming that field's
+        // change of the face below (side 0) or above (side 1) the cell; the
+        // group's first lane sums the two faces as serial_correction does.
+        // (Longer lists: the redundant linear faces of the field lanes cost
+        // more than the shorter chains save on one CU.)
+        const unsigned int i = threadIdx.x / 8;
+        const int j = threadIdx.x % 8, side = j / NV, k = j % NV;
+        unsigned long long e = 0ull;
+        if (i < nl) e = s.list[i];
+        const long long off = (long long)((e >> 8) & 0xffffffffull);
+        const unsigned cm = i < nl ? (unsigned)(e & 0xffu) : 0u;
+        double dF[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dF[v] = 0.0;
+        if (j < 2 * NV && ((cm >> side) & 1u))
+          face_delta_field<NV, 0, SPLIT, HYB>(Uk, g, ph, ctl->lf_bits[0], (int)off, 0, 0, side, k,
+                                              (lane & ~7) + side * NV, dF);
+        double dm[NV], dp[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          dm[v] = __shfl(dF[v], (lane & ~7), 64);
+          dp[v] = __shfl(dF[v], (lane & ~7) + NV, 64);
+        }
+        if (i < nl && j == 0) {
+          double acc[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+          if (cm & 1u) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += 1.0 * dm[v];
+          }
+          if (cm & 2u) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += -1.0 * dp[v];
+          }
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            out[v * g.ncell + off] = out[v * g.ncell + off] + (rb * dt) * (acc[v] * ph.inv_dx);
+        }
+      } else {
+        const bool grouped = (unsigned long long)nl * FIX_GRP <= (unsigned long long)nthr;
+        const unsigned int stride = grouped ? nthr / FIX_GRP : nthr;
+        for (unsigned int i = grouped ? threadIdx.x / FIX_GRP : threadIdx.x; i < nl; i += stride) {
+          const unsigned long long e = s.list[i];
+          double un[NV];
+          row_fix_cell<NV, SPLIT, HYB>(Uk, out, ctl, g, ph, (long long)((e >> 8) & 0xffffffffull),
+                                       (unsigned)(e & 0xffu), rb * dt, grouped, un);
+        }
       }
       __syncthreads();
     }
