@@ -310,7 +310,8 @@ struct ListTurn {
 };
 
 hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, double* out,
-                      const double* Un, double ra, double rb, bool fold_cfl = false) {
+                      const double* Un, double ra, double rb, bool fold_cfl = false,
+                      bool kclock = false) {
   ListTurn turn(c);
   RowLaunch L;
   L.Uk = Uk;
@@ -330,6 +331,9 @@ hipError_t launch_row(const weno_l2is_ctx* c, int out_kind, const double* Uk, do
   L.list_n = turn.cur;
   L.list_clear = turn.next;
   L.cfl = fold_cfl ? c->ctl : nullptr;
+  L.clock = kclock ? c->ctl : nullptr;
+  L.cfl_dx = c->p.cfl * c->dx;
+  L.s_floor = c->inflow_speed;
   L.fo_D = c->path == WL2_PATH_FUSED_CELLS ? nullptr : c->fo_D;
   L.fo_map = c->fo_map;
   L.fo_cap = (unsigned int)c->ncell;
@@ -441,13 +445,17 @@ hipError_t rhs_into(const weno_l2is_ctx* c, const double* Uk, double* out) {
 // One RK stage: out = a Un + b (Uk + dt L(Uk)).  fold_cfl (fused 3D and row
 // 1D/2D paths): the stage kernels also fold the CFL maximum of `out` into
 // the control word.
+// kclock (1D/2D stage 1): the step's dt has not been formed yet; the stage
+// kernel forms it (finalize_dt_kernel's rule) and the clock still reads the
+// step's start, which the ghost rows take as their time (tc = 0).
 hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, double* out,
-                 double ra, double rb, double tc, bool fold_cfl = false) {
+                 double ra, double rb, double tc, bool fold_cfl = false, bool kclock = false) {
   hipError_t e;
-  e = c->p.split == WL2_SPLIT_LF ? launch_lf(c, Uk, tc) : fill_yghosts(c, Uk, tc);
+  const double tg = kclock ? -1.0 : tc;  // -1: the clock's t
+  e = c->p.split == WL2_SPLIT_LF ? launch_lf(c, Uk, tg) : fill_yghosts(c, Uk, tg);
   if (e != hipSuccess) return e;
   if (use_fused(c)) return launch_fused(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
-  if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl);
+  if (use_row(c)) return launch_row(c, OUT_RK, Uk, out, Un, ra, rb, fold_cfl, kclock);
   for (int d = 0; d < c->dim - 1; ++d) {
     SweepArgs a{Uk, c->acc, nullptr, nullptr, c->ctl, 0.0, 1.0};
     if ((e = launch_sweep(c, d, d == 0 ? OUT_WRITE : OUT_ACCUM, a)) != hipSuccess) return e;
@@ -456,10 +464,10 @@ hipError_t stage(const weno_l2is_ctx* c, const double* Uk, const double* Un, dou
   return launch_sweep(c, c->dim - 1, OUT_RK, a);
 }
 
-hipError_t rk3(const weno_l2is_ctx* c, double* U, bool fold_cfl = false) {
+hipError_t rk3(const weno_l2is_ctx* c, double* U, bool fold_cfl = false, bool kclock = false) {
   hipError_t e;
   // the stages at the times t0, t0 + dt, t0 + dt/2 of the Shu-Osher form
-  if ((e = stage(c, U, nullptr, c->U1, 0.0, 1.0, 0.0)) != hipSuccess) return e;
+  if ((e = stage(c, U, nullptr, c->U1, 0.0, 1.0, 0.0, false, kclock)) != hipSuccess) return e;
   if ((e = stage(c, c->U1, U, c->U2, 0.75, 0.25, 1.0)) != hipSuccess) return e;
   return stage(c, c->U2, U, U, 1.0 / 3.0, 2.0 / 3.0, 0.5, fold_cfl);
 }
@@ -812,8 +820,11 @@ int weno_l2is_advance(weno_l2is_ctx* c, double* U, int n_steps, double t_end) {
   // one call U is only touched here, so the folded maximum is that of U.
   const bool fold = use_fused(c) || use_row(c);
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
-    e = launch_cfl(c, U, 0.0, 1, fold && s > 0);
-    if (e == hipSuccess) e = rk3(c, U, fold && s + 1 < n_steps);
+    // 1D/2D: from the second step the stage-1 kernel forms dt itself from
+    // the folded maximum (one launch per step less)
+    const bool kclock = s > 0 && use_row(c);
+    if (!kclock) e = launch_cfl(c, U, 0.0, 1, fold && s > 0);
+    if (e == hipSuccess) e = rk3(c, U, fold && s + 1 < n_steps, kclock);
   }
   return hip_err(e);
 }

@@ -122,6 +122,20 @@ __device__ __forceinline__ double cfl_take(StepCtl* ctl) {
   return __longlong_as_double((long long)m);
 }
 
+// The running maximum over all slots read by one whole wavefront (lane s
+// reads slot s; every lane gets the maximum), the slots left as they are.
+__device__ __forceinline__ double cfl_peek_wave(const StepCtl* ctl) {
+  static_assert(CFL_SLOTS <= 64, "one slot per lane");
+  const int lane = threadIdx.x & 63;
+  unsigned long long m = lane < CFL_SLOTS ? ctl->smax[lane].bits : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long q = __shfl_xor(m, o, 64);
+    m = q > m ? q : m;
+  }
+  return __longlong_as_double((long long)m);
+}
+
 // cfl_take by one whole wavefront (lane s reads and clears slot s): one
 // round trip to memory instead of CFL_SLOTS.  Every lane gets the maximum.
 __device__ __forceinline__ double cfl_take_wave(StepCtl* ctl) {
@@ -138,6 +152,39 @@ __device__ __forceinline__ double cfl_take_wave(StepCtl* ctl) {
     m = q > m ? q : m;
   }
   return __longlong_as_double((long long)m);
+}
+
+// The device-clock dt of a step from the CFL maximum folded by the step
+// before, by finalize_dt_kernel's rule, formed by every wavefront of a
+// stage-1 kernel itself (all of its lanes call; every wavefront reads the
+// same slots and clock, so gets the same bits).  The lane with writer set
+// records t0 = t, dt and the step count; it leaves t and the slots alone,
+// which other wavefronts still read: the stage's correction kernel sets
+// t = t0 + dt (the same value as t + dt) and clears the slots
+// (clock_commit).
+__device__ __forceinline__ double clock_dt_wave(StepCtl* ctl, double cfl_dx, double s_floor,
+                                                bool writer) {
+  double smax = cfl_peek_wave(ctl);
+  if (s_floor > smax) smax = s_floor;
+  double dt = cfl_dx / smax;
+  const double t = ctl->t, te = ctl->t_end;
+  const bool stop = !(t < te) || ctl->status != 0u;
+  if (stop) dt = 0.0;
+  else if (t + dt > te) dt = te - t;
+  if (writer) {
+    ctl->t0 = t;
+    ctl->dt = dt;
+    if (!stop) ctl->steps += 1u;
+  }
+  return dt;
+}
+
+// After every wavefront of the stage-1 kernel has read the clock: t = t0 +
+// dt (t itself when the clock stopped, dt = 0) and the CFL slots cleared for
+// the step's own fold (one thread).
+__device__ __forceinline__ void clock_commit(StepCtl* ctl) {
+  ctl->t = ctl->t0 + ctl->dt;
+  cfl_clear(ctl);
 }
 
 // ---------------------------------------------------------------- CFL

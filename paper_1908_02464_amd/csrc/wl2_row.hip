@@ -49,7 +49,8 @@ hipError_t row1d_steps(double* U, double* U1, double* U2, StepCtl* ctl, unsigned
 hipError_t row_fix(const RowLaunch& L) {
   const RowArgs a{L.Uk,   L.out,    L.Un, L.ctl,        L.rk_a,
                   L.rk_b, L.list,   L.list_n, 0ull, L.list_clear,
-                  L.out_kind == OUT_RK ? L.cfl : nullptr};
+                  L.out_kind == OUT_RK ? L.cfl : nullptr, L.out_kind == OUT_RK ? L.clock : nullptr,
+                  L.cfl_dx, L.s_floor};
   const dim3 fg(1024), fb(128);
   // the per-cell kernel: 2048 workgroups, so that lists of up to 16384
   // cells take its field-parallel mode (workgroups past the list's end
@@ -99,7 +100,8 @@ hipError_t row_fix(const RowLaunch& L) {
 hipError_t row_launch(const RowLaunch& L) {
   const RowArgs a{L.Uk,   L.out,  L.Un,     L.ctl, L.rk_a,
                   L.rk_b, L.list, L.list_n, 0ull,  nullptr,
-                  L.out_kind == OUT_RK ? L.cfl : nullptr};
+                  L.out_kind == OUT_RK ? L.cfl : nullptr, L.out_kind == OUT_RK ? L.clock : nullptr,
+                  L.cfl_dx, L.s_floor};
   const int tiles_x = (L.g.n[0] + RT - 1) / RT;
   const int ych = L.nvar == 3 ? 1 : (L.ych < 1 ? 1 : (L.ych > ROW_MAX_YCH ? ROW_MAX_YCH : L.ych));
   const long long chunks = L.nvar == 3 ? 1 : (L.g.n[1] + ych - 1) / ych;

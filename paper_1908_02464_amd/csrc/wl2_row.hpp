@@ -39,6 +39,12 @@ struct RowArgs {
                              // correction kernel
   StepCtl* cfl;              // RK: if set, fold the CFL speed of the new state
                              // into cfl->smax / status (next step's dt)
+  StepCtl* clock;            // RK stage 1 of a step whose CFL maximum the step
+                             // before folded: the stage kernel forms the step's
+                             // dt itself (clock_dt_wave, with cfl_dx and the
+                             // inflow speed floor s_floor) and its correction
+                             // kernel commits the clock (clock_commit); else null
+  double cfl_dx, s_floor;
 };
 
 // Entry of the correction list: tag | element offset << 8 | face mask (bit 0
@@ -455,6 +461,7 @@ template <int NV, int OUT, int SPLIT, int HYB>
 __global__ __launch_bounds__(128) void row_fix_kernel(RowArgs a, KGrid g, KPhys ph) {
   // the next stage's list starts empty (no kernel of this stage uses it)
   if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
+  if (a.clock != nullptr && blockIdx.x == 0 && threadIdx.x == 0) clock_commit(a.clock);
   double scale = 1.0;
   if (OUT == OUT_RK) {
     const double dt = a.ctl->dt;
@@ -498,6 +505,7 @@ __global__ __launch_bounds__(128) void row_face_kernel(RowArgs a, KGrid g, KPhys
                                                        unsigned int* map, unsigned int cap) {
   // the next stage's list starts empty (no kernel of this stage uses it)
   if (a.list_clear != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.list_clear = 0u;
+  if (a.clock != nullptr && blockIdx.x == 0 && threadIdx.x == 0) clock_commit(a.clock);
   if (OUT == OUT_RK && !(a.ctl->dt > 0.0)) return;
   constexpr int ND = NV - 2;
   const unsigned int n = *a.list_n;
@@ -770,7 +778,9 @@ __global__ __launch_bounds__(RW, 2) void row_kernel(RowArgs a, KGrid g, KPhys ph
   __shared__ double ring[2][NV + 3][RW];
   double dt = 0.0;
   if (OUT == OUT_RK) {
-    dt = a.ctl->dt;
+    dt = a.clock != nullptr
+             ? clock_dt_wave(a.clock, a.cfl_dx, a.s_floor, blockIdx.x == 0 && threadIdx.x == 0)
+             : a.ctl->dt;
     if (!(dt > 0.0)) return;  // finished run: leave the state untouched
   }
   const int item = blockIdx.x;

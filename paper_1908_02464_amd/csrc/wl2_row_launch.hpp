@@ -25,6 +25,9 @@ struct RowLaunch {
   unsigned int* list_n;
   unsigned int* list_clear;  // the next stage's counter, zeroed by the correction kernel
   StepCtl* cfl;              // RK: fold the CFL speed of the new state here (or null)
+  StepCtl* clock;            // RK stage 1: the stage kernel forms the step's dt
+                             // from the CFL maximum folded here (or null)
+  double cfl_dx, s_floor;    // with clock: CFL number x dx, inflow speed floor
   // face-once corrections (2D, long lists): per-entry face changes
   // [2][nvar][fo_cap] and the cell -> entry map [ncell]; null: per cell
   double* fo_D;
